@@ -1,0 +1,133 @@
+"""Pins for the step-by-step lookup model (section 6) and for the first-error reading.
+
+The GPU validator computes, like the paper, the positions where the lookup
+checks fire; the first such position d is turned into the first-error offset s
+(the start of the first ill-formed character) by
+
+    s = max{ k in [max(0, d-3), d] : b[k-1] < 0xC0, b[k-2] < 0xE0, b[k-3] < 0xF0 }
+
+(bytes before the start count as zero), i.e. the latest position at most three
+bytes back that does not sit inside an unfinished character.  These tests check
+that reading exhaustively against the branchy oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import lookup_model as lm
+from conftest import read_golden_rows
+from paper_2010_03090_amd import synth
+
+
+def test_table9_worked_example():
+    rows = read_golden_rows("table9_classification.txt")
+    b = np.array(rows["input"], np.uint8)
+    prev1, r1, r2, r3, sc = lm.classify(b)
+    assert prev1.tolist() == rows["prev1"]
+    assert (prev1 >> 4).tolist() == rows["prev1_high"]
+    assert (prev1 & 0xF).tolist() == rows["prev1_low"]
+    assert (b >> 4).tolist() == rows["input_high"]
+    assert r1.tolist() == rows["byte_1_high"]
+    assert r2.tolist() == rows["byte_1_low"]
+    assert r3.tolist() == rows["byte_2_high"]
+    assert sc.tolist() == rows["and"]
+    # section 6.2: the two-continuation marks are exactly where they are required
+    assert (lm.must_be_2_3_continuation(b) == sc).all()
+    assert lm.validate(bytes(b))
+
+
+# Table 8: one representative (byte 1, byte 2) pair per error pattern, and the bit it must set
+# (bit names follow the order implied by Table 9).
+TABLE8_PAIRS = [
+    (0x41, 0x80, lm.TOO_LONG), (0x00, 0xBF, lm.TOO_LONG),
+    (0xC3, 0x41, lm.TOO_SHORT), (0xE9, 0xC3, lm.TOO_SHORT), (0xF0, 0x00, lm.TOO_SHORT),
+    (0xC0, 0x80, lm.OVERLONG_2 | 0), (0xC1, 0xBF, lm.OVERLONG_2),
+    (0xED, 0xA0, lm.SURROGATE), (0xED, 0xBF, lm.SURROGATE),
+    (0xE0, 0x80, lm.OVERLONG_3), (0xE0, 0x9F, lm.OVERLONG_3),
+    (0xF0, 0x80, lm.OVERLONG_4), (0xF0, 0x8F, lm.OVERLONG_4), (0xF5, 0x80, lm.OVERLONG_4),
+    (0xF4, 0x90, lm.TOO_LARGE), (0xF4, 0xBF, lm.TOO_LARGE), (0xFF, 0xA0, lm.TOO_LARGE),
+    (0x80, 0x80, lm.TWO_CONTS), (0xBF, 0xBF, lm.TWO_CONTS),
+]
+
+
+@pytest.mark.parametrize("b1,b2,bit", TABLE8_PAIRS)
+def test_table8_patterns_set_their_bit(b1, b2, bit):
+    sc = lm.classify(np.array([b1, b2], np.uint8))[4][1]
+    assert sc & bit, (hex(b1), hex(b2), hex(sc))
+
+
+def test_valid_pairs_have_no_error_bits():
+    """Every pair of bytes that can occur inside valid text sets no bit 0-6 (section 6.1)."""
+    cps = [c for c in range(0x110000) if not 0xD800 <= c <= 0xDFFF]
+    data = np.frombuffer("".join(chr(c) for c in cps).encode(), np.uint8)
+    sc = lm.classify(data)[4]
+    assert not (sc & 0x7F).any()
+    assert (sc & 0x80 == lm.must_be_2_3_continuation(data)).all()
+
+
+def _all_strings(n):
+    if n == 0:
+        return np.zeros((1, 0), np.uint8)
+    v = np.arange(256 ** n, dtype=np.uint32)
+    return np.stack([(v >> (8 * k)) & 0xFF for k in range(n)], axis=1).astype(np.uint8)
+
+
+def _resolve(strs, err):
+    """First-error offsets from per-position lookup errors (GPU reading), -1 where none fired."""
+    nz = err != 0
+    any_err = nz.any(axis=1)
+    d = np.where(any_err, nz.argmax(axis=1), 0)
+    n = strs.shape[1]
+    pad = np.concatenate([np.zeros((strs.shape[0], 3), np.uint8), strs], axis=1)  # pad[:, k+3] = b[k]
+
+    def byte(k):  # b[k] with zeros outside the string (k may be negative)
+        kk = np.clip(k + 3, 0, n + 2)
+        vals = pad[np.arange(strs.shape[0]), np.minimum(kk, pad.shape[1] - 1)]
+        return np.where((k >= 0) & (k < n), vals, 0)
+
+    s = d.copy()
+    found = np.zeros(strs.shape[0], bool)
+    for back in range(0, 4):
+        k = d - back
+        ok = (k >= 0) & (byte(k - 1) < 0xC0) & (byte(k - 2) < 0xE0) & (byte(k - 3) < 0xF0) & ~found
+        s = np.where(ok, k, s)
+        found |= ok
+    assert found[any_err].all()
+    return np.where(any_err, s, -1)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_lookup_model_and_reading_exhaustive(n):
+    strs = _all_strings(n)
+    err = lm.position_errors(strs)
+    offsets = np.arange(strs.shape[0] + 1, dtype=np.int64) * n
+    flags, ferr = oracle.first_error_batch(strs.reshape(-1), offsets)
+    assert np.array_equal((err == 0).all(axis=1), flags.astype(bool))
+    assert np.array_equal(_resolve(strs, err), ferr)
+
+
+ALPHA = np.array([0x00, 0x41, 0x7F, 0x80, 0x8F, 0x90, 0x9F, 0xA0, 0xBF, 0xC0, 0xC1, 0xC2, 0xDF, 0xE0, 0xE1,
+                  0xEC, 0xED, 0xEE, 0xEF, 0xF0, 0xF1, 0xF3, 0xF4, 0xF5, 0xF7, 0xF8, 0xFF], np.uint8)
+
+
+@pytest.mark.parametrize("n", [4, 5])
+def test_lookup_model_and_reading_boundary_alphabet(n):
+    idx = np.indices((ALPHA.size,) * n).reshape(n, -1).T
+    strs = ALPHA[idx]
+    err = lm.position_errors(strs)
+    offsets = np.arange(strs.shape[0] + 1, dtype=np.int64) * n
+    flags, ferr = oracle.first_error_batch(strs.reshape(-1), offsets)
+    assert np.array_equal((err == 0).all(axis=1), flags.astype(bool))
+    assert np.array_equal(_resolve(strs, err), ferr)
+
+
+def test_lookup_model_with_ascii_blocks_on_longer_inputs():
+    """The 64-byte ASCII path (section 6.4) gives the same decision on texts with one error."""
+    rng = np.random.default_rng(3)
+    for seed in range(40):
+        variant = ["ascii", "latin", "mixed", "cjk"][seed % 4]
+        n = int(rng.integers(1, 700))
+        buf = synth.text(n, variant, seed)
+        if seed % 2:
+            synth.inject_random(buf, seed)
+        assert lm.validate(bytes(buf)) == (oracle.first_error(buf) < 0), (seed, variant, n)
