@@ -1,0 +1,145 @@
+/*
+ * utf8v -- lookup UTF-8 validation on AMD Instinct MI355X (gfx950).
+ *
+ * Implements the lookup algorithm of Keiser & Lemire, "Validating UTF-8 In Less
+ * Than One Instruction Per Byte" (section 6): every byte is classified together
+ * with its predecessor through three 16-entry nibble tables ANDed into an
+ * error-class byte (section 6.1, tables following the error patterns of
+ * Table 8), required third/fourth continuation bytes are checked (section
+ * 6.2), the end of the input must not cut a character (section 6.3), and
+ * all-ASCII spans skip the classification (section 6.4).
+ *
+ * What is computed.  A byte string is valid when it is a concatenation of the
+ * well-formed characters of Table 1 (section 2), i.e. it breaks none of the
+ * six rules of section 3 (5+ byte lead, too short, too long, overlong, too
+ * large, surrogate).  The paper decides validity only; this library also
+ * reports the FIRST-ERROR OFFSET: the length of the longest valid prefix made
+ * of whole characters (the start of the first ill-formed character), or -1
+ * when the string is valid.  The empty string is valid.
+ *
+ * Memory.  Every buffer pointer given to these functions must be device
+ * accessible (hipMalloc memory, a torch CUDA tensor, managed or pinned host
+ * memory) unless it is documented as a host pointer.  The caller owns all
+ * buffers; the library never frees or retains them.  The library owns a small
+ * per-(device, stream) workspace (created on first use, freed by
+ * utf8v_release).
+ *
+ * Errors.  Functions returning int return UTF8V_OK (0) or a negative status.
+ * Invalid UTF-8 is a result, never an error.  No function aborts or throws.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the default
+ * stream).  *_async functions only enqueue work; the others synchronize the
+ * stream before returning.  Calls that overlap on one stream are ordered by
+ * the stream; the library serializes its own workspace per stream.
+ */
+#ifndef UTF8V_H
+#define UTF8V_H
+
+#include <stdbool.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UTF8V_OK 0
+#define UTF8V_EINVAL (-1)     /* NULL pointer with a non-zero size, n < 0, bad offsets, bad config */
+#define UTF8V_ENOTDEVICE (-2) /* a pointer the GPU cannot access (pageable host memory) */
+#define UTF8V_EHIP (-3)       /* HIP runtime error; utf8v_last_hip_error() has the code */
+#define UTF8V_ENOMEM (-4)     /* workspace allocation failed */
+
+/*
+ * utf8_validate -- true iff buf[0..len) is valid UTF-8 (section 6 lookup
+ * algorithm over one buffer).  buf may be NULL iff len == 0.  Synchronous on
+ * the default stream.  On misuse it returns false and sets utf8v_last_status().
+ */
+bool utf8_validate(const uint8_t *buf, size_t len);
+
+/*
+ * utf8v_validate_ex -- validate buf[0..len) on `stream`, wait, and store the
+ * first-error offset (-1 if valid) in *first_err (a HOST pointer, may be NULL).
+ * Returns 1 if valid, 0 if invalid, or a negative status.
+ */
+int utf8v_validate_ex(const uint8_t *buf, size_t len, int64_t *first_err, void *stream);
+
+/*
+ * utf8v_validate_async -- enqueue the validation of buf[0..len) on `stream`;
+ * the first-error offset (-1 if valid) is written to *dev_first_err (a DEVICE
+ * pointer to one int64) when the stream reaches it.  No host synchronization.
+ */
+int utf8v_validate_async(const uint8_t *buf, size_t len, int64_t *dev_first_err, void *stream);
+
+/*
+ * utf8_validate_batch -- validate n strings given in CSR form: string k is
+ * data[offsets[k] .. offsets[k+1]).  offsets has n+1 entries (device memory),
+ * non-decreasing, offsets[0] >= 0 (need not be 0).  Every string is a stream of
+ * its own: the bytes before its start count as zero and its end gets the end
+ * check (section 6.3).  Outputs (device memory, n entries each):
+ *   out_flags[k]     = 1 if string k is valid UTF-8, else 0;
+ *   out_first_err[k] = first-error offset RELATIVE to the string start, or -1.
+ * n == 0 is a no-op.  Synchronous on the default stream.  Offsets are trusted:
+ * decreasing or out-of-range offsets give undefined results (use
+ * utf8v_check_offsets first when they come from untrusted input).
+ */
+int utf8_validate_batch(const uint8_t *data, const int64_t *offsets, int64_t n,
+                        uint8_t *out_flags, int64_t *out_first_err);
+
+/* utf8v_validate_batch_async -- as utf8_validate_batch, enqueued on `stream`. */
+int utf8v_validate_batch_async(const uint8_t *data, const int64_t *offsets, int64_t n,
+                               uint8_t *out_flags, int64_t *out_first_err, void *stream);
+
+/*
+ * utf8v_check_offsets -- 1 if offsets[0..n] (device memory) is non-decreasing
+ * with offsets[0] >= 0, else 0; negative status on error.  Synchronous.
+ */
+int utf8v_check_offsets(const int64_t *offsets, int64_t n, void *stream);
+
+/* ---- tuning (see utf8v_tune_* in the Python package for the autotuner) ------------ */
+
+typedef struct {
+  int32_t unroll;            /* single buffer: dwordx4 loads per lane per tile, 1, 2, 4 or 8 */
+  int32_t waves_per_cu;      /* single buffer: persistent waves per compute unit, >= 1 */
+  int32_t ascii;             /* 1: skip classification of all-ASCII 1 KiB slabs (section 6.4) */
+  int32_t batch_blocks_per_cu; /* batch: persistent 256-thread blocks per compute unit, >= 1 */
+  int32_t batch_ascii;       /* batch: 1 = ASCII skip per wave chunk */
+} utf8v_config;
+
+/* Read / replace the launch configuration of the calling process (all devices). */
+int utf8v_get_config(utf8v_config *cfg);
+int utf8v_set_config(const utf8v_config *cfg);
+
+/* ---- diagnostics and measurement -------------------------------------------------- */
+
+/*
+ * utf8v_classify -- for positions 0..len of buf (device), write the section 6.1
+ * classification byte to sc[i] and the per-position error byte (classification
+ * XOR the section 6.2 requirement) to err[i]; position len is the end check on
+ * a virtual zero byte.  sc and err are device arrays of len+1 bytes.  Async.
+ */
+int utf8v_classify(const uint8_t *buf, size_t len, uint8_t *sc, uint8_t *err, void *stream);
+
+/*
+ * utf8v_read_ceiling / utf8v_copy -- plain streaming kernels over len bytes
+ * (len a multiple of 16, 16-byte aligned device buffers) used as the measured
+ * memory ceiling next to the validator.  read_ceiling ORs words into *dev_out.
+ */
+int utf8v_read_ceiling(const uint8_t *buf, size_t len, uint32_t *dev_out, void *stream);
+int utf8v_copy(const uint8_t *src, uint8_t *dst, size_t len, void *stream);
+
+/* Status of the last call on this host thread, its message, and the last HIP error code. */
+int utf8v_last_status(void);
+const char *utf8v_strerror(int status);
+int utf8v_last_hip_error(void);
+
+/* Number of compute units of the current device (0 if no device). */
+int utf8v_num_cus(void);
+
+/* Free the workspaces of the calling process.  No call may be in flight. */
+int utf8v_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UTF8V_H */

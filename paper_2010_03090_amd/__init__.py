@@ -1,0 +1,141 @@
+"""MI355X-native lookup UTF-8 validation (Keiser & Lemire, section 6) -- Python API.
+
+Thin wrappers over the C-ABI of ``libutf8v.so``: PyTorch provides device
+memory and streams, the library's HIP kernels do all the work.
+
+    import torch, paper_2010_03090_amd as u8
+    buf = torch.frombuffer(bytearray("héllo".encode()), dtype=torch.uint8).cuda()
+    u8.validate(buf)                 # True
+    u8.first_error(buf)              # -1
+    flags, first_err = u8.validate_batch(data, offsets)   # CSR strings
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _native
+from ._native import Config, Utf8vError, check, load
+
+__all__ = ["validate", "first_error", "validate_async", "validate_batch", "validate_batch_async",
+           "classify", "check_offsets", "get_config", "set_config", "num_cus", "read_ceiling", "copy",
+           "Config", "Utf8vError", "load"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None) -> int | None:
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    h = s.cuda_stream
+    return h or None
+
+
+def _dev_u8(t, name="buf"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA uint8 tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def first_error(buf, stream=None) -> int:
+    """First-error offset of a CUDA uint8 tensor (-1 if it is valid UTF-8). Synchronizes the stream."""
+    _dev_u8(buf)
+    out = ctypes.c_int64(0)
+    check(load().utf8v_validate_ex(buf.data_ptr() if buf.numel() else None, buf.numel(), ctypes.byref(out),
+                                   _stream_handle(stream)), "utf8v_validate_ex")
+    return int(out.value)
+
+
+def validate(buf, stream=None) -> bool:
+    """True iff the CUDA uint8 tensor holds valid UTF-8."""
+    return first_error(buf, stream) < 0
+
+
+def validate_async(buf, out, stream=None) -> None:
+    """Enqueue validation; out (CUDA int64 tensor, 1 element) receives the first-error offset."""
+    torch = _torch()
+    _dev_u8(buf)
+    if out.dtype != torch.int64 or not out.is_cuda or out.numel() < 1:
+        raise TypeError("out must be a CUDA int64 tensor")
+    check(load().utf8v_validate_async(buf.data_ptr() if buf.numel() else None, buf.numel(), out.data_ptr(),
+                                      _stream_handle(stream)), "utf8v_validate_async")
+
+
+def validate_batch_async(data, offsets, flags, first_err, stream=None) -> None:
+    torch = _torch()
+    _dev_u8(data, "data")
+    n = offsets.numel() - 1
+    if offsets.dtype != torch.int64 or not offsets.is_cuda or n < 0:
+        raise TypeError("offsets must be a CUDA int64 tensor with n+1 entries")
+    if n == 0:
+        return
+    check(load().utf8v_validate_batch_async(data.data_ptr() if data.numel() else offsets.data_ptr(),
+                                            offsets.data_ptr(), n, flags.data_ptr(), first_err.data_ptr(),
+                                            _stream_handle(stream)), "utf8v_validate_batch_async")
+
+
+def validate_batch(data, offsets, stream=None):
+    """Validate CSR strings data[offsets[k]:offsets[k+1]]; returns (flags uint8, first_err int64) on the device.
+
+    first_err is relative to each string start, -1 for valid strings.  The
+    result tensors are ready when the given (or current) stream reaches them.
+    """
+    torch = _torch()
+    n = offsets.numel() - 1
+    flags = torch.empty(max(n, 0), dtype=torch.uint8, device=offsets.device)
+    ferr = torch.empty(max(n, 0), dtype=torch.int64, device=offsets.device)
+    validate_batch_async(data, offsets, flags, ferr, stream)
+    return flags, ferr
+
+
+def check_offsets(offsets, stream=None) -> bool:
+    n = offsets.numel() - 1
+    return bool(check(load().utf8v_check_offsets(offsets.data_ptr(), n, _stream_handle(stream)),
+                      "utf8v_check_offsets"))
+
+
+def classify(buf, stream=None):
+    """Per-position (classification byte, error byte) tensors of length len+1 (diagnostic)."""
+    torch = _torch()
+    _dev_u8(buf)
+    sc = torch.empty(buf.numel() + 1, dtype=torch.uint8, device=buf.device)
+    err = torch.empty_like(sc)
+    check(load().utf8v_classify(buf.data_ptr() if buf.numel() else None, buf.numel(), sc.data_ptr(),
+                                err.data_ptr(), _stream_handle(stream)), "utf8v_classify")
+    return sc, err
+
+
+def read_ceiling(buf, out, stream=None) -> None:
+    check(load().utf8v_read_ceiling(buf.data_ptr(), buf.numel(), out.data_ptr(), _stream_handle(stream)),
+          "utf8v_read_ceiling")
+
+
+def copy(src, dst, stream=None) -> None:
+    check(load().utf8v_copy(src.data_ptr(), dst.data_ptr(), src.numel(), _stream_handle(stream)), "utf8v_copy")
+
+
+def get_config() -> dict:
+    c = Config()
+    check(load().utf8v_get_config(ctypes.byref(c)), "utf8v_get_config")
+    return c.as_dict()
+
+
+def set_config(**kw) -> dict:
+    """Update launch parameters (unroll, waves_per_cu, ascii, batch_blocks_per_cu, batch_ascii)."""
+    c = Config()
+    check(load().utf8v_get_config(ctypes.byref(c)), "utf8v_get_config")
+    for k, v in kw.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, int(v))
+    check(load().utf8v_set_config(ctypes.byref(c)), "utf8v_set_config")
+    return c.as_dict()
+
+
+def num_cus() -> int:
+    return int(load().utf8v_num_cus())

@@ -1,0 +1,301 @@
+// C-ABI of the gfx950 validator library (declared in include/utf8v.h).
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "../../include/utf8v.h"
+#include "common.hpp"
+
+namespace {
+
+using utf8v::kNone;
+
+thread_local int g_last_status = UTF8V_OK;
+thread_local int g_last_hip = 0;
+
+std::mutex g_mu;
+utf8v_config g_cfg = {4, 16, 1, 4, 1};
+
+struct Workspace {
+  unsigned long long* dmin = nullptr;  // device: first detection position (kNone = none)
+  int64_t* result = nullptr;           // device: first-error offset of the last call
+  int* flag = nullptr;                 // device: scratch flag (offset checks)
+  int64_t* host = nullptr;             // pinned host copy of result / flag
+};
+
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+std::map<int, int> g_cus;
+
+int set_status(int s) { g_last_status = s; return s; }
+
+int hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  (void)hipGetLastError();
+  return set_status(e == hipErrorOutOfMemory ? UTF8V_ENOMEM : UTF8V_EHIP);
+}
+
+int current_device(int* dev) {
+  hipError_t e = hipGetDevice(dev);
+  return e == hipSuccess ? UTF8V_OK : hip_fail(e);
+}
+
+int num_cus_of(int dev) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_cus.find(dev);
+  if (it != g_cus.end()) return it->second;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) {
+    (void)hipGetLastError();
+    v = 0;
+  }
+  g_cus[dev] = v;
+  return v;
+}
+
+// Workspace of (current device, stream); created on first use with dmin = none.
+int workspace(hipStream_t st, Workspace** out) {
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(dev, st);
+  auto it = g_ws.find(key);
+  if (it != g_ws.end()) { *out = &it->second; return UTF8V_OK; }
+  Workspace w;
+  hipError_t e = hipMalloc(&w.dmin, 64);
+  if (e == hipSuccess) e = hipHostMalloc(&w.host, 64, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    if (w.dmin) (void)hipFree(w.dmin);
+    return hip_fail(e);
+  }
+  w.result = reinterpret_cast<int64_t*>(w.dmin) + 1;
+  w.flag = reinterpret_cast<int*>(w.dmin + 2);
+  const unsigned long long init[3] = {kNone, 0, 0};
+  e = hipMemcpy(w.dmin, init, sizeof init, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(w.dmin);
+    (void)hipHostFree(w.host);
+    return hip_fail(e);
+  }
+  auto res = g_ws.emplace(key, w);
+  *out = &res.first->second;
+  return UTF8V_OK;
+}
+
+// 0 if the GPU can dereference p, else UTF8V_ENOTDEVICE.
+int check_device_ptr(const void* p) {
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_status(UTF8V_ENOTDEVICE);
+  }
+  if (attr.type == hipMemoryTypeUnregistered) return set_status(UTF8V_ENOTDEVICE);
+  return UTF8V_OK;
+}
+
+utf8v::TuneSingle tune_single() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  utf8v::TuneSingle t;
+  t.unroll = g_cfg.unroll;
+  t.waves_per_cu = g_cfg.waves_per_cu;
+  t.ascii = g_cfg.ascii;
+  return t;
+}
+
+utf8v::TuneBatch tune_batch() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  utf8v::TuneBatch t;
+  t.blocks_per_cu = g_cfg.batch_blocks_per_cu;
+  t.ascii = g_cfg.batch_ascii;
+  return t;
+}
+
+int enqueue_single(const uint8_t* buf, size_t len, int64_t* dev_out, hipStream_t st, Workspace** ws_out) {
+  if (buf == nullptr && len != 0) return set_status(UTF8V_EINVAL);
+  if (len != 0) {
+    int rc = check_device_ptr(buf);
+    if (rc) return rc;
+  }
+  Workspace* ws = nullptr;
+  int rc = workspace(st, &ws);
+  if (rc) return rc;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const int cus = num_cus_of(dev);
+  hipError_t e = utf8v::launch_single(buf, (uint64_t)len, ws->dmin, dev_out ? dev_out : ws->result, tune_single(),
+                                      cus > 0 ? cus : 1, st);
+  if (e != hipSuccess) return hip_fail(e);
+  if (ws_out) *ws_out = ws;
+  return set_status(UTF8V_OK);
+}
+
+}  // namespace
+
+extern "C" {
+
+int utf8v_validate_ex(const uint8_t* buf, size_t len, int64_t* first_err, void* stream) {
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Workspace* ws = nullptr;
+  int rc = enqueue_single(buf, len, nullptr, st, &ws);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(ws->host, ws->result, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e);
+  const int64_t r = *ws->host;
+  if (first_err) *first_err = r;
+  set_status(UTF8V_OK);
+  return r < 0 ? 1 : 0;
+}
+
+bool utf8_validate(const uint8_t* buf, size_t len) {
+  return utf8v_validate_ex(buf, len, nullptr, nullptr) == 1;
+}
+
+int utf8v_validate_async(const uint8_t* buf, size_t len, int64_t* dev_first_err, void* stream) {
+  if (dev_first_err == nullptr) return set_status(UTF8V_EINVAL);
+  int rc = check_device_ptr(dev_first_err);
+  if (rc) return rc;
+  return enqueue_single(buf, len, dev_first_err, reinterpret_cast<hipStream_t>(stream), nullptr);
+}
+
+int utf8v_validate_batch_async(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* out_flags,
+                               int64_t* out_first_err, void* stream) {
+  if (n < 0) return set_status(UTF8V_EINVAL);
+  if (n == 0) return set_status(UTF8V_OK);
+  if (!data || !offsets || !out_flags || !out_first_err) return set_status(UTF8V_EINVAL);
+  for (const void* p : {(const void*)data, (const void*)offsets, (const void*)out_flags, (const void*)out_first_err}) {
+    int rc = check_device_ptr(p);
+    if (rc) return rc;
+  }
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  const int cus = num_cus_of(dev);
+  hipError_t e = utf8v::launch_batch(data, offsets, n, out_flags, out_first_err, tune_batch(), cus > 0 ? cus : 1,
+                                     reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e);
+  return set_status(UTF8V_OK);
+}
+
+int utf8_validate_batch(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* out_flags,
+                        int64_t* out_first_err) {
+  int rc = utf8v_validate_batch_async(data, offsets, n, out_flags, out_first_err, nullptr);
+  if (rc) return rc;
+  hipError_t e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) return hip_fail(e);
+  return set_status(UTF8V_OK);
+}
+
+int utf8v_check_offsets(const int64_t* offsets, int64_t n, void* stream) {
+  if (n < 0 || offsets == nullptr) return set_status(UTF8V_EINVAL);
+  int rc = check_device_ptr(offsets);
+  if (rc) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Workspace* ws = nullptr;
+  rc = workspace(st, &ws);
+  if (rc) return rc;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const int cus = num_cus_of(dev);
+  hipError_t e = hipMemsetAsync(ws->flag, 0, sizeof(int), st);
+  if (e == hipSuccess) e = utf8v::launch_offsets_check(offsets, n, ws->flag, cus > 0 ? cus : 1, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(ws->host, ws->flag, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e);
+  set_status(UTF8V_OK);
+  return *reinterpret_cast<int*>(ws->host) ? 0 : 1;
+}
+
+int utf8v_get_config(utf8v_config* cfg) {
+  if (!cfg) return set_status(UTF8V_EINVAL);
+  std::lock_guard<std::mutex> lk(g_mu);
+  *cfg = g_cfg;
+  return set_status(UTF8V_OK);
+}
+
+int utf8v_set_config(const utf8v_config* cfg) {
+  if (!cfg) return set_status(UTF8V_EINVAL);
+  const bool ok = (cfg->unroll == 1 || cfg->unroll == 2 || cfg->unroll == 4 || cfg->unroll == 8) &&
+                  cfg->waves_per_cu >= 1 && cfg->waves_per_cu <= 4096 && (cfg->ascii == 0 || cfg->ascii == 1) &&
+                  cfg->batch_blocks_per_cu >= 1 && cfg->batch_blocks_per_cu <= 64 &&
+                  (cfg->batch_ascii == 0 || cfg->batch_ascii == 1);
+  if (!ok) return set_status(UTF8V_EINVAL);
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cfg = *cfg;
+  return set_status(UTF8V_OK);
+}
+
+int utf8v_classify(const uint8_t* buf, size_t len, uint8_t* sc, uint8_t* err, void* stream) {
+  if ((buf == nullptr && len != 0) || sc == nullptr || err == nullptr) return set_status(UTF8V_EINVAL);
+  for (const void* p : {(const void*)sc, (const void*)err}) {
+    int rc = check_device_ptr(p);
+    if (rc) return rc;
+  }
+  if (len) {
+    int rc = check_device_ptr(buf);
+    if (rc) return rc;
+  }
+  hipError_t e = utf8v::launch_classify(buf, (uint64_t)len, sc, err, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e);
+  return set_status(UTF8V_OK);
+}
+
+int utf8v_read_ceiling(const uint8_t* buf, size_t len, uint32_t* dev_out, void* stream) {
+  if (!buf || !dev_out || (len & 15) || (reinterpret_cast<uintptr_t>(buf) & 15)) return set_status(UTF8V_EINVAL);
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  hipError_t e = utf8v::launch_read_ceiling(buf, len, dev_out, num_cus_of(dev), reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e);
+  return set_status(UTF8V_OK);
+}
+
+int utf8v_copy(const uint8_t* src, uint8_t* dst, size_t len, void* stream) {
+  if (!src || !dst || (len & 15) || ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15))
+    return set_status(UTF8V_EINVAL);
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  hipError_t e = utf8v::launch_copy(src, dst, len, num_cus_of(dev), reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e);
+  return set_status(UTF8V_OK);
+}
+
+int utf8v_last_status(void) { return g_last_status; }
+int utf8v_last_hip_error(void) { return g_last_hip; }
+
+const char* utf8v_strerror(int status) {
+  switch (status) {
+    case UTF8V_OK: return "ok";
+    case UTF8V_EINVAL: return "invalid argument";
+    case UTF8V_ENOTDEVICE: return "pointer not accessible by the GPU";
+    case UTF8V_EHIP: return "HIP runtime error";
+    case UTF8V_ENOMEM: return "out of device memory";
+    default: return "unknown status";
+  }
+}
+
+int utf8v_num_cus(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return num_cus_of(dev);
+}
+
+int utf8v_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : g_ws) {
+    (void)hipFree(kv.second.dmin);
+    (void)hipHostFree(kv.second.host);
+  }
+  g_ws.clear();
+  return set_status(UTF8V_OK);
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Device-side lookup UTF-8 validation (Keiser & Lemire, section 6), four bytes
+// per 32-bit register ("SWAR"), for gfx950.
+//
+// Byte k of a register holds stream position 4*j + k (little-endian).  For a
+// register x and the register p that precedes it in the stream:
+//
+//   prev1 = the stream shifted by one byte   (section 6.1; v_alignbyte_b32)
+//   byte_1_high[prev1 >> 4] & byte_1_low[prev1 & 15] & byte_2_high[x >> 4]
+//                                            (section 6.1, three 16-entry tables)
+//   ^ must23                                 (section 6.2: 0x80 where the byte two
+//                                             back is >= 0xE0 or three back >= 0xF0)
+//
+// A non-zero byte of the result marks a position where the input is not UTF-8.
+//
+// The tables are the paper's three nibble tables (bit order of Table 9; their
+// contents follow from the error patterns of Table 8):
+//
+//   byte_1_high  02 02 02 02 02 02 02 02 80 80 80 80 21 01 15 49
+//   byte_1_low   E7 A3 83 83 8B CB CB CB CB CB CB CB CB DB CB CB
+//   byte_2_high  01 01 01 01 01 01 01 01 E6 AE BA BA 01 01 01 01
+//
+// A 16-entry lookup of four bytes at once is done with v_perm_b32, which picks
+// bytes out of an 8-byte pool: the low three bits of a nibble select within a
+// half-table and bit 3 picks the half.  byte_1_high and byte_2_high have a
+// constant low half (0x02 and 0x01), so one v_perm_b32 on the high half is
+// merged with the constant under a sign-bit mask; byte_1_low needs both halves,
+// merged by a second v_perm_b32.  v_perm_b32's selectors 8..11 return the sign
+// of pool bytes 1, 3, 5, 7 spread over a whole byte, which turns a pair of
+// shifted registers into a 0x00/0xFF sign mask in one instruction.  v_lerp_u8
+// computes (a + b) >> 1 per byte without carries between bytes, so bit 7 of
+// lerp(v, 0x20) is exactly "v >= 0xE0" (the unsigned comparisons of sections
+// 6.2-6.3).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace utf8v {
+
+// Pools: v_perm_b32(hi, lo, sel) picks byte sel (0..7) of the 64-bit value hi:lo.
+constexpr uint32_t kB1H_HI_LO = 0x80808080u;  // byte_1_high[8..11]
+constexpr uint32_t kB1H_HI_HI = 0x49150121u;  // byte_1_high[12..15]
+constexpr uint32_t kB1L_LO_LO = 0x8383A3E7u;  // byte_1_low[0..3]
+constexpr uint32_t kB1L_LO_HI = 0xCBCBCB8Bu;  // byte_1_low[4..7]
+constexpr uint32_t kB1L_HI_LO = 0xCBCBCBCBu;  // byte_1_low[8..11]
+constexpr uint32_t kB1L_HI_HI = 0xCBCBDBCBu;  // byte_1_low[12..15]
+constexpr uint32_t kB2H_HI_LO = 0xBABAAEE6u;  // byte_2_high[8..11]
+constexpr uint32_t kB2H_HI_HI = 0x01010101u;  // byte_2_high[12..15]
+constexpr uint32_t kB1H_LOW_HALF = 0x02020202u;  // byte_1_high[0..7]
+constexpr uint32_t kB2H_LOW_HALF = 0x01010101u;  // byte_2_high[0..7]
+
+// Selector turning (x, x shifted up one byte) into a per-byte sign mask.
+constexpr uint32_t kSignSel = 0x0B090A08u;
+
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+  return __builtin_amdgcn_perm(hi, lo, sel);
+}
+__device__ __forceinline__ uint32_t align(uint32_t hi, uint32_t lo, uint32_t bytes) {
+  return __builtin_amdgcn_alignbyte(hi, lo, bytes);
+}
+// Per byte: bit 7 of the result is set iff v >= 256 - k (k a byte constant).
+__device__ __forceinline__ uint32_t ge_mask7(uint32_t v, uint32_t k) {
+  return __builtin_amdgcn_lerp(v, k, 0u);
+}
+// (m & a) | (~m & b)
+__device__ __forceinline__ uint32_t select_bits(uint32_t m, uint32_t a, uint32_t b) {
+  return __builtin_amdgcn_bitop3_b32(m, a, b, 0xCA);
+}
+__device__ __forceinline__ uint32_t and3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x80);
+}
+// (a | b) & c
+__device__ __forceinline__ uint32_t or_and(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0xA8);
+}
+
+// Section 6.1: the classification byte of each position (AND of the three lookups).
+// prev1 holds the byte before each position, prev2 the byte two before.
+__device__ __forceinline__ uint32_t classify(uint32_t x, uint32_t prev1, uint32_t prev2) {
+  const uint32_t sh2 = (x >> 4) & 0x07070707u;       // high nibble of the byte, low 3 bits
+  const uint32_t sh1 = (prev1 >> 4) & 0x07070707u;   // high nibble of prev1, low 3 bits
+  const uint32_t sl1 = prev1 & 0x07070707u;          // low nibble of prev1, low 3 bits
+  const uint32_t neg2 = perm(x, prev1, kSignSel);      // 0xFF where byte >= 0x80 (high nibble >= 8)
+  const uint32_t neg1 = perm(prev1, prev2, kSignSel);  // 0xFF where prev1 >= 0x80
+  // bit 3 of prev1's low nibble selects the byte_1_low half: byte k reads pool byte k or 4+k
+  const uint32_t half = ((prev1 >> 1) & 0x04040404u) | 0x03020100u;
+  const uint32_t byte_1_high = select_bits(neg1, perm(kB1H_HI_HI, kB1H_HI_LO, sh1), kB1H_LOW_HALF);
+  const uint32_t byte_1_low = perm(perm(kB1L_HI_HI, kB1L_HI_LO, sl1), perm(kB1L_LO_HI, kB1L_LO_LO, sl1), half);
+  const uint32_t byte_2_high = select_bits(neg2, perm(kB2H_HI_HI, kB2H_HI_LO, sh2), kB2H_LOW_HALF);
+  return and3(byte_1_high, byte_1_low, byte_2_high);
+}
+
+// Section 6.2: 0x80 where a second continuation byte is required.
+__device__ __forceinline__ uint32_t must23(uint32_t prev2, uint32_t prev3) {
+  return or_and(ge_mask7(prev2, 0x20202020u), ge_mask7(prev3, 0x10101010u), 0x80808080u);
+}
+
+// Per-position error bytes of register x preceded by register p (sections 6.1-6.2).
+__device__ __forceinline__ uint32_t position_errors(uint32_t x, uint32_t p) {
+  const uint32_t prev1 = align(x, p, 3);
+  const uint32_t prev2 = align(x, p, 2);
+  const uint32_t prev3 = align(x, p, 1);
+  return classify(x, prev1, prev2) ^ must23(prev2, prev3);
+}
+
+// Section 6.3 on the three bytes before a position: non-zero iff a character is
+// still open there (last byte >= 0xC0, second-to-last >= 0xE0, third-to-last >= 0xF0).
+// p holds those bytes in its top three bytes.
+__device__ __forceinline__ uint32_t open_at_end(uint32_t p) {
+  const uint32_t c = ge_mask7(p, 0x40404040u) & 0x80000000u;  // byte 3 >= 0xC0
+  const uint32_t e = ge_mask7(p, 0x20202020u) & 0x00800000u;  // byte 2 >= 0xE0
+  const uint32_t f = ge_mask7(p, 0x10101010u) & 0x00008000u;  // byte 1 >= 0xF0
+  return c | e | f;
+}
+
+// Index (0..3) of the lowest non-zero byte of a non-zero register.
+__device__ __forceinline__ int first_byte(uint32_t e) { return __builtin_ctz(e) >> 3; }
+
+}  // namespace utf8v

@@ -1,0 +1,186 @@
+// Single-buffer lookup validation (section 6 of Keiser & Lemire) for gfx950.
+//
+// Layout.  Positions are byte offsets from the buffer start.  The interior
+// [i0, i1) is the largest 16-byte-aligned part of the buffer; it is cut into
+// wave tiles of U KiB.  In a tile, slab u (1 KiB) is read by one
+// global_load_dwordx4 per lane (lane l reads bytes 16*l .. 16*l+15 of the slab),
+// so every load instruction of a wave covers 1 KiB of consecutive bytes.  The
+// up-to-15-byte head and tail outside the interior are validated by the
+// finalize kernel, with the bytes outside the buffer read as zero.
+//
+// The three bytes before each 16-byte chunk (the paper's previous register,
+// section 6.1) come from the neighbouring lane through DPP (wave_ror:1); lane 0
+// takes the last dword of the previous slab, and the first slab of a wave's
+// first tile reads it from memory (zero before the buffer start, section 6).
+//
+// Errors are ORed into a per-lane register (section 6, "error register").  Only
+// when it is non-zero does a lane recompute its chunk to find its first
+// detection position; the wave's minimum then goes to one 64-bit atomicMin.
+// The finalize kernel turns the overall first detection position d into the
+// first-error offset s (the start of the first ill-formed character):
+//   s = max{ k in [max(0, d-3), d] : no character is open at k }.
+#include "common.hpp"
+#include "lookup.hpp"
+
+namespace utf8v {
+
+// Dword of bytes [pos-4, pos), zero below position 0.  (buf + pos) is 16-byte aligned.
+__device__ __forceinline__ uint32_t prev_dword(const uint8_t* __restrict__ buf, uint64_t pos) {
+  if (pos >= 4) return *reinterpret_cast<const uint32_t*>(buf + pos - 4);
+  uint32_t v = 0;
+  for (uint64_t j = 0; j < pos; ++j) v |= (uint32_t)buf[j] << (8 * (4 - pos + j));
+  return v;
+}
+
+template <int U, bool ASCII, bool FULL>
+__device__ __forceinline__ void single_tile(const uint8_t* __restrict__ buf, uint64_t base, uint64_t i1, int lane,
+                                            uint32_t& carry, uint64_t& dmin) {
+  uint4 x[U];
+  bool live[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint64_t pos = base + (uint64_t)u * 1024 + (uint64_t)lane * 16;
+    live[u] = FULL || pos < i1;
+    if (FULL || live[u]) x[u] = *reinterpret_cast<const uint4*>(buf + pos);
+    else x[u] = make_uint4(0, 0, 0, 0);
+  }
+  uint32_t prev[U];
+  uint32_t acc = 0;
+  const bool lane0 = lane == 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    // previous dword: lane l-1's last dword; lane 0 gets the previous slab's lane 63
+    const uint32_t rot = __builtin_amdgcn_update_dpp(0u, x[u].w, kDppWaveRor1, 0xF, 0xF, false);
+    prev[u] = lane0 ? carry : rot;
+    carry = rot;  // lane 0 now holds lane 63's last dword of this slab
+    if (ASCII) {
+      // Section 6.4: when the slab and the three bytes before it are all ASCII,
+      // no check can fire in it (an ASCII byte after ASCII bytes is never an
+      // error), so the classification is skipped for the whole wave.
+      const uint32_t hi = (x[u].x | x[u].y | x[u].z | x[u].w | prev[u]) & 0x80808080u;
+      if (__all(hi == 0)) continue;
+    }
+    uint32_t e = position_errors(x[u].x, prev[u]);
+    e |= position_errors(x[u].y, x[u].x);
+    e |= position_errors(x[u].z, x[u].y);
+    e |= position_errors(x[u].w, x[u].z);
+    acc |= (FULL || live[u]) ? e : 0u;
+  }
+  if (__builtin_expect(acc != 0, 0) && dmin == kNone) {
+    // first detection position of this lane (exact recomputation, rare)
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!(FULL || live[u])) continue;
+      const uint32_t w[5] = {prev[u], x[u].x, x[u].y, x[u].z, x[u].w};
+      const uint64_t pos = base + (uint64_t)u * 1024 + (uint64_t)lane * 16;
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t e = position_errors(w[j + 1], w[j]);
+        if (e && dmin == kNone) dmin = pos + 4 * j + first_byte(e);
+      }
+      if (dmin != kNone) break;
+    }
+  }
+}
+
+template <int U, bool ASCII>
+__global__ __launch_bounds__(256) void single_main(SingleArgs a) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint64_t W = (uint64_t)U * 1024;
+  uint64_t t = wave * a.tiles_per_wave;
+  const uint64_t t_end = t + a.tiles_per_wave < a.tiles ? t + a.tiles_per_wave : a.tiles;
+  if (t >= t_end) return;
+  uint64_t dmin = kNone;
+  uint32_t carry = prev_dword(a.buf, a.i0 + t * W);
+  for (; t < t_end; ++t) {
+    const uint64_t base = a.i0 + t * W;
+    if (base + W <= a.i1) single_tile<U, ASCII, true>(a.buf, base, a.i1, lane, carry, dmin);
+    else single_tile<U, ASCII, false>(a.buf, base, a.i1, lane, carry, dmin);
+  }
+  wave_min_to(a.dmin, dmin, lane);
+}
+
+// Head and tail chunks, the end check (section 6.3), and d -> s.
+__global__ void single_finalize(FinalizeArgs a) {
+  if (threadIdx.x != 0) return;
+  const uint8_t* buf = a.buf;
+  const int64_t n = (int64_t)a.n;
+  uint64_t d = *a.dmin;
+  auto byte_at = [&](int64_t p) -> uint32_t { return (p >= 0 && p < n) ? buf[p] : 0u; };
+  auto chunk = [&](int64_t c) {
+    uint32_t w[5];
+    for (int k = 0; k < 5; ++k) {
+      uint32_t v = 0;
+      for (int b = 0; b < 4; ++b) v |= byte_at(c - 4 + 4 * k + b) << (8 * b);
+      w[k] = v;
+    }
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t e = position_errors(w[j + 1], w[j]);
+      if (e) {
+        const int64_t p = c + 4 * j + first_byte(e);
+        if (p >= 0 && (uint64_t)p < d) d = (uint64_t)p;
+        break;
+      }
+    }
+  };
+  if (a.i0 > 0) chunk((int64_t)a.i0 - 16);
+  if ((int64_t)a.i1 < n) chunk((int64_t)a.i1);
+  if (n > 0) {
+    uint32_t p = 0;
+    for (int b = 0; b < 4; ++b) p |= byte_at(n - 4 + b) << (8 * b);
+    if (open_at_end(p) && (uint64_t)n < d) d = (uint64_t)n;
+  }
+  int64_t s = -1;
+  if (d != kNone) {
+    const int64_t dd = (int64_t)d;
+    s = dd;  // unreachable fallback: one of the four candidates always closes
+    for (int64_t k = dd; k >= 0 && k >= dd - 3; --k) {
+      if (byte_at(k - 1) < 0xC0 && byte_at(k - 2) < 0xE0 && byte_at(k - 3) < 0xF0) { s = k; break; }
+    }
+  }
+  *a.out = s;
+  *a.dmin = kNone;
+}
+
+// ---- launch -----------------------------------------------------------------------------
+
+template <int U, bool ASCII>
+static hipError_t launch_single_t(const SingleArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((single_main<U, ASCII>), dim3(grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_single(const uint8_t* buf, uint64_t n, unsigned long long* dmin, int64_t* out,
+                         const TuneSingle& cfg, int num_cus, hipStream_t st) {
+  const uint64_t mis = (uint64_t)(reinterpret_cast<uintptr_t>(buf) & 15);
+  const uint64_t i0 = mis ? 16 - mis : 0;
+  uint64_t i1 = i0;
+  if (n > i0) i1 = i0 + ((n - i0) & ~uint64_t(15));
+  if (i1 > i0) {
+    const int U = cfg.unroll;
+    const uint64_t W = (uint64_t)U * 1024;
+    SingleArgs a;
+    a.buf = buf; a.i0 = i0; a.i1 = i1; a.dmin = dmin;
+    a.tiles = (i1 - i0 + W - 1) / W;
+    const uint64_t max_waves = (uint64_t)num_cus * (uint64_t)cfg.waves_per_cu;
+    a.tiles_per_wave = (a.tiles + max_waves - 1) / max_waves;
+    if (a.tiles_per_wave < (uint64_t)cfg.min_tiles_per_wave) a.tiles_per_wave = cfg.min_tiles_per_wave;
+    const uint64_t waves = (a.tiles + a.tiles_per_wave - 1) / a.tiles_per_wave;
+    const int grid = (int)((waves + 3) / 4);
+    hipError_t e;
+    const bool asc = cfg.ascii != 0;
+    switch (U) {
+      case 1: e = asc ? launch_single_t<1, true>(a, grid, st) : launch_single_t<1, false>(a, grid, st); break;
+      case 2: e = asc ? launch_single_t<2, true>(a, grid, st) : launch_single_t<2, false>(a, grid, st); break;
+      case 8: e = asc ? launch_single_t<8, true>(a, grid, st) : launch_single_t<8, false>(a, grid, st); break;
+      default: e = asc ? launch_single_t<4, true>(a, grid, st) : launch_single_t<4, false>(a, grid, st); break;
+    }
+    if (e != hipSuccess) return e;
+  }
+  FinalizeArgs f;
+  f.buf = buf; f.n = n; f.i0 = i0; f.i1 = i1; f.dmin = dmin; f.out = out;
+  hipLaunchKernelGGL(single_finalize, dim3(1), dim3(64), 0, st, f);
+  return hipGetLastError();
+}
+
+}  // namespace utf8v

@@ -1,0 +1,66 @@
+"""The C-ABI library loads and exports every symbol include/utf8v.h declares (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2010_03090_amd import _native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "utf8v.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(utf8v?_\w+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("utf8_validate", "utf8_validate_batch", "utf8v_validate_ex", "utf8v_validate_async",
+                     "utf8v_validate_batch_async", "utf8v_strerror", "utf8v_last_status", "utf8v_release"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    lib = _native.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+        assert name in _native.SIGNATURES, name
+    assert set(_native.SIGNATURES) == set(_declared())
+
+
+def test_host_only_error_paths():
+    lib = _native.load()
+    assert lib.utf8v_strerror(0) == b"ok"
+    assert lib.utf8v_strerror(_native.UTF8V_EINVAL) == b"invalid argument"
+    # argument checks happen before any device call
+    assert lib.utf8_validate_batch(None, None, -1, None, None) == _native.UTF8V_EINVAL
+    assert lib.utf8v_validate_ex(None, 5, None, None) == _native.UTF8V_EINVAL
+    assert lib.utf8v_last_status() == _native.UTF8V_EINVAL
+    assert lib.utf8v_validate_async(None, 0, None, None) == _native.UTF8V_EINVAL
+    assert lib.utf8v_validate_batch_async(None, None, 0, None, None, None) == 0   # n == 0 is a no-op
+    assert lib.utf8_validate(None, 3) is False
+
+
+def test_config_roundtrip_and_validation():
+    import paper_2010_03090_amd as u8
+    old = u8.get_config()
+    try:
+        new = u8.set_config(unroll=2, waves_per_cu=8, ascii=0)
+        assert new["unroll"] == 2 and new["waves_per_cu"] == 8 and new["ascii"] == 0
+        with pytest.raises(u8.Utf8vError):
+            u8.set_config(unroll=3)
+        with pytest.raises(u8.Utf8vError):
+            u8.set_config(waves_per_cu=0)
+        assert u8.get_config()["unroll"] == 2
+    finally:
+        u8.set_config(**old)
+
+
+def test_library_is_in_tree_and_for_gfx950():
+    assert os.path.dirname(_native.LIB_PATH) == os.path.join(ROOT, "paper_2010_03090_amd")
+    blob = open(_native.LIB_PATH, "rb").read()
+    assert b"gfx950" in blob

@@ -1,0 +1,286 @@
+"""GPU parity: the HIP validator against the oracle, element by element (needs an MI355X).
+
+Bit-exact comparison of flags and first-error offsets (integer results, no
+tolerance).  Inputs are seeded and synthetic (paper_2010_03090_amd.synth).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import lookup_model as lm
+from conftest import read_golden_rows, read_labelled_vectors
+from paper_2010_03090_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def u8():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2010_03090_amd as u8
+    u8.load()
+    return u8
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_table9_on_gpu(u8):
+    say("case: table9")
+    rows = read_golden_rows("table9_classification.txt")
+    b = np.array(rows["input"], np.uint8)
+    sc, err = u8.classify(dev(b))
+    sc = sc.cpu().numpy()
+    assert sc[: b.size].tolist() == rows["and"]
+    assert not err.cpu().numpy().any()
+
+
+def test_classification_matches_lookup_model(u8):
+    """Per-position classification and error bytes equal the section 6 model on varied buffers."""
+    bufs = []
+    pairs = np.stack(np.meshgrid(np.arange(256), np.arange(256), indexing="ij"), -1).reshape(-1).astype(np.uint8)
+    bufs.append(pairs)                                           # every (prev, byte) pair
+    alpha = np.array([0x00, 0x41, 0x7F, 0x80, 0x8F, 0x90, 0x9F, 0xA0, 0xBF, 0xC0, 0xC1, 0xC2, 0xDF, 0xE0,
+                      0xE1, 0xEC, 0xED, 0xEE, 0xEF, 0xF0, 0xF1, 0xF3, 0xF4, 0xF5, 0xF7, 0xF8, 0xFF], np.uint8)
+    bufs.append(alpha[np.indices((27,) * 4).reshape(4, -1).T].reshape(-1))   # all 4-sequences of the alphabet
+    rng = np.random.default_rng(11)
+    bufs.append(rng.integers(0, 256, 100_003, dtype=np.uint8))
+    for v in ("mixed", "cjk", "emoji"):
+        b = synth.text(50_001, v, 3)
+        synth.inject_random(b, 5)
+        bufs.append(b)
+    for i, b in enumerate(bufs):
+        say(f"case: classify buffer {i} len {b.size}")
+        sc, err = u8.classify(dev(b))
+        padded = np.concatenate([b, [0]]).astype(np.uint8)
+        exp_sc = lm.classify(padded)[4]
+        exp_err = exp_sc ^ lm.must_be_2_3_continuation(padded)
+        assert np.array_equal(sc.cpu().numpy(), exp_sc), i
+        assert np.array_equal(err.cpu().numpy(), exp_err), i
+
+
+def test_labelled_vectors_single(u8):
+    for b, exp, label, src in read_labelled_vectors():
+        say(f"case: labelled {b.hex()} {label}")
+        assert u8.first_error(dev(np.frombuffer(b, np.uint8))) == exp, (label, src)
+
+
+def test_empty_and_tiny(u8):
+    say("case: empty")
+    assert u8.first_error(torch.empty(0, dtype=torch.uint8, device="cuda")) == -1
+    for v in range(256):
+        b = np.array([v], np.uint8)
+        assert u8.first_error(dev(b)) == oracle.first_error(b)
+
+
+def test_single_error_at_every_offset_and_alignment(u8):
+    """One injected error at each offset around chunk, lane, slab and tile boundaries, unaligned bases."""
+    rng = np.random.default_rng(21)
+    base_len = 9000
+    big = dev(np.zeros(base_len + 64, np.uint8))
+    positions = sorted(set(list(range(0, 80)) + [k + d for k in (1024, 2048, 3072, 4096, 8192 - 16)
+                                                 for d in range(-6, 7)] + list(rng.integers(0, base_len, 200))))
+    checked = 0
+    for variant in ("mixed", "latin", "ascii", "emoji"):
+        clean = synth.text(base_len, variant, 7)
+        for pos in positions:
+            for cls in range(7):
+                if (pos + cls) % 3:
+                    continue
+                buf = clean.copy()
+                if cls == 6:
+                    cut = int(pos) % 40 + 1
+                    buf = buf[: max(1, base_len - cut)].copy()
+                    s = synth.inject(buf, 0, 6, pos)
+                else:
+                    s = synth.inject(buf, int(pos), cls, int(pos) * 7 + cls)
+                if s < 0:
+                    continue
+                shift = int(pos) % 16
+                big[shift: shift + buf.size].copy_(torch.from_numpy(buf))
+                view = big[shift: shift + buf.size]
+                got = u8.first_error(view)
+                exp = oracle.first_error(buf)
+                assert exp == s
+                assert got == exp, (variant, int(pos), cls, shift, got, exp)
+                checked += 1
+    say(f"checked {checked} single-error buffers")
+
+
+def test_sizes_and_alignments_valid_and_random(u8):
+    big = dev(np.zeros(70_000, np.uint8))
+    sizes = list(range(0, 70)) + [1023, 1024, 1025, 4095, 4096, 4097, 16384 + 5, 65536 - 1, 65536 + 3]
+    for n in sizes:
+        for shift in (0, 1, 7, 15):
+            for variant in ("mixed", "random"):
+                b = synth.text(n, variant, n * 31 + shift)
+                big[shift: shift + n].copy_(torch.from_numpy(b))
+                got = u8.first_error(big[shift: shift + n])
+                assert got == oracle.first_error(b), (n, shift, variant)
+
+
+def test_config0_mixed_1mib_and_64_corrupted_copies(u8):
+    say("case: config0")
+    clean, copies = synth.single_buffer_with_errors(1 << 20, "mixed", 0, 64)
+    assert u8.first_error(dev(clean)) == -1 == oracle.first_error(clean)
+    for buf, s, cls in copies:
+        assert u8.first_error(dev(buf)) == s == oracle.first_error(buf), cls
+
+
+@pytest.mark.parametrize("variant", ["ascii", "latin", "cjk", "emoji", "random"])
+def test_config1_full_size_1gib(u8, variant):
+    """1 GiB buffers at the benchmark's launch configuration, plus the copy with an error in the last 4 bytes."""
+    say(f"case: config1 {variant}")
+    n = 1 << 30
+    seed = {"ascii": 1, "latin": 2, "cjk": 3, "emoji": 4, "random": 5}[variant]
+    b = synth.text(n, variant, seed)
+    t = dev(b)
+    exp = oracle.first_error(b)
+    assert u8.first_error(t) == exp
+    if variant != "random":
+        assert exp == -1
+        tail, s, cls = synth.tail_error_copy(b[-64:], seed)
+        t[-64:].copy_(torch.from_numpy(tail))
+        assert u8.first_error(t) == s + n - 64
+    del t
+    torch.cuda.empty_cache()
+
+
+def test_batch_exhaustive_short_strings(u8):
+    """Every string of length 0..3 in one CSR batch (each at many alignments)."""
+    say("case: batch exhaustive <= 3")
+    parts, lens = [], []
+    for n in range(0, 4):
+        if n == 0:
+            parts.append(np.zeros(0, np.uint8)); lens += [0] * 3
+            continue
+        v = np.arange(256 ** n, dtype=np.uint32)
+        strs = np.stack([(v >> (8 * k)) & 0xFF for k in range(n)], 1).astype(np.uint8)
+        parts.append(strs.reshape(-1))
+        lens += [n] * strs.shape[0]
+    data = np.concatenate(parts)
+    lens = np.array(lens, np.int64)
+    offsets = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    f_o, e_o = oracle.first_error_batch(data, offsets)
+    flags, ferr = u8.validate_batch(dev(data), dev(offsets))
+    torch.cuda.synchronize()
+    assert np.array_equal(ferr.cpu().numpy(), e_o)
+    assert np.array_equal(flags.cpu().numpy(), f_o)
+
+
+def test_batch_semantics(u8):
+    """offsets[0] != 0, empty strings, strings across tiles, and each string alone == in the batch."""
+    rng = np.random.default_rng(5)
+    lens = np.concatenate([rng.integers(0, 9, 400), rng.integers(0, 5000, 40), [0, 0, 1, 0, 70000, 0]])
+    rng.shuffle(lens)
+    for base in (0, 3, 4096 + 13):
+        say(f"case: batch semantics base {base}")
+        data, offsets, expected = synth.batch_from_lengths(lens, "mixed", 9 + base, err_frac=0.3, base=base)
+        f_o, e_o = oracle.first_error_batch(data, offsets)
+        assert np.array_equal(e_o[expected >= 0], expected[expected >= 0])
+        td = dev(data)
+        flags, ferr = u8.validate_batch(td, dev(offsets))
+        torch.cuda.synchronize()
+        ferr = ferr.cpu().numpy()
+        assert np.array_equal(ferr, e_o)
+        assert np.array_equal(flags.cpu().numpy(), f_o)
+        for k in rng.choice(lens.size, 50, replace=False):
+            s, e = int(offsets[k]), int(offsets[k + 1])
+            alone = u8.first_error(td[s:e]) if e > s else -1
+            assert alone == ferr[k]
+
+
+def test_batch_random_bytes_and_tiny_strings(u8):
+    rng = np.random.default_rng(8)
+    lens = rng.integers(0, 6, 200_000)
+    offsets = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    data = rng.integers(0, 256, int(offsets[-1]), dtype=np.uint8)
+    say("case: batch random tiny")
+    f_o, e_o = oracle.first_error_batch(data, offsets)
+    flags, ferr = u8.validate_batch(dev(data), dev(offsets))
+    torch.cuda.synchronize()
+    assert np.array_equal(ferr.cpu().numpy(), e_o)
+    assert np.array_equal(flags.cpu().numpy(), f_o)
+
+
+def test_batch_config2_full_size(u8):
+    """1,000,000 log-normal strings (median 64 B, sigma 1.2), 1% with an injected error."""
+    say("case: config2")
+    data, offsets, expected = synth.lognormal_batch(1_000_000, 2)
+    f_o, e_o = oracle.first_error_batch(data, offsets)
+    assert np.array_equal(e_o[expected >= 0], expected[expected >= 0])
+    flags, ferr = u8.validate_batch(dev(data), dev(offsets))
+    torch.cuda.synchronize()
+    assert np.array_equal(ferr.cpu().numpy(), e_o)
+    assert np.array_equal(flags.cpu().numpy(), f_o)
+    assert int((f_o == 0).sum()) >= 10_000
+
+
+def test_batch_config3_heavy_tail(u8):
+    """20,000 Pareto strings (alpha 1.1, 1 KiB .. 64 MiB), per-string variants, 0.5% errors."""
+    say("case: config3a")
+    data, offsets, expected = synth.pareto_batch(20_000, 3)
+    f_o, e_o = oracle.first_error_batch(data, offsets)
+    flags, ferr = u8.validate_batch(dev(data), dev(offsets))
+    torch.cuda.synchronize()
+    assert np.array_equal(ferr.cpu().numpy(), e_o)
+    assert np.array_equal(flags.cpu().numpy(), f_o)
+    assert np.array_equal(e_o[expected >= 0], expected[expected >= 0])
+
+
+def test_tuning_invariance(u8):
+    """Every launch configuration gives identical results."""
+    old = u8.get_config()
+    bufs = [synth.text(300_001, "mixed", 1), synth.text(70_000, "ascii", 2), synth.text(5000, "random", 3)]
+    b = synth.text(200_000, "latin", 4)
+    synth.inject(b, 150_000, 2, 4)
+    bufs.append(b)
+    expected = [oracle.first_error(x) for x in bufs]
+    data, offsets, _ = synth.lognormal_batch(20_000, 6)
+    f_o, e_o = oracle.first_error_batch(data, offsets)
+    td, to = dev(data), dev(offsets)
+    tb = [dev(x) for x in bufs]
+    try:
+        for unroll in (1, 2, 4, 8):
+            for ascii_ in (0, 1):
+                for waves in (1, 3, 16, 4096):
+                    u8.set_config(unroll=unroll, ascii=ascii_, waves_per_cu=waves,
+                                  batch_blocks_per_cu=max(1, waves % 9), batch_ascii=ascii_)
+                    for t, e in zip(tb, expected):
+                        assert u8.first_error(t) == e, (unroll, ascii_, waves)
+                    flags, ferr = u8.validate_batch(td, to)
+                    torch.cuda.synchronize()
+                    assert np.array_equal(ferr.cpu().numpy(), e_o), (unroll, ascii_, waves)
+    finally:
+        u8.set_config(**old)
+
+
+def test_async_and_streams(u8):
+    b = synth.text(1 << 20, "cjk", 9)
+    synth.inject(b, 777_777, 4, 1)
+    t = dev(b)
+    out = torch.empty(4, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        u8.validate_async(t, out[1:2])
+    s.synchronize()
+    assert int(out[1]) == oracle.first_error(b)
+    assert u8.first_error(t, stream=s) == oracle.first_error(b)
+
+
+def test_pageable_host_pointer_rejected(u8):
+    import ctypes
+    buf = ctypes.create_string_buffer(b"abc")
+    lib = u8.load()
+    assert lib.utf8v_validate_ex(ctypes.addressof(buf), 3, None, None) == -2
