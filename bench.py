@@ -1,0 +1,307 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X lookup UTF-8 validator (one JSON line on stdout).
+
+Headline workload (the single-buffer configuration of the metric): 1 GiB
+buffers of synthetic text, five seeded variants -- pure ASCII, Latin-like
+(85% 1-byte / 15% 2-byte), CJK-like (10% 1-byte / 90% 3-byte), emoji-heavy
+(40% 1-byte / 60% 4-byte) and uniform random bytes -- plus, for each valid
+variant, a copy with one error in its last 4 bytes.  One step validates all
+nine buffers once (9 GiB); buffers are resident in HBM before timing starts.
+
+Also reported: the measured read ceiling of the same buffers (a plain OR
+reduction, the GPU analogue of the paper's memcpy column), the batched
+workload (1,000,000 log-normal strings) against one launch per string, and the
+CPU oracle on a bounded sample (a baseline, not a target).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "validated GB/s & % HBM peak (1 GiB buffer); batched strings/s; p99 latency"
+HBM_PEAK_GBPS = 8000.0        # MI355X published HBM3E bandwidth
+GIB = 1 << 30
+VARIANTS = [("ascii", 1), ("latin", 2), ("cjk", 3), ("emoji", 4), ("random", 5)]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=GIB, help="bytes per single buffer")
+    ap.add_argument("--batch-strings", type=int, default=1_000_000)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bounded oracle sample time")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the validator shards by contiguous byte ranges with a 3-byte halo; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU (MI355X)", file=sys.stderr)
+        sys.exit(1)
+    import paper_2010_03090_amd as u8
+    from paper_2010_03090_amd import synth
+    lib = u8.load()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream or None
+
+    # ---- inputs (generated on the host, copied to HBM before timing) ---------------------
+    n = args.size
+    t0 = time.time()
+    bufs, names, expected = [], [], []
+    host = {}
+    for name, seed in VARIANTS:
+        h = synth.text(n, name, seed)
+        host[name] = h
+        bufs.append(torch.from_numpy(h).to(dev))
+        names.append(name)
+        expected.append(None)
+    for name, seed in VARIANTS[:4]:
+        t = bufs[names.index(name)].clone()
+        tail, s, cls = synth.tail_error_copy(host[name][-64:], seed)
+        t[-64:].copy_(torch.from_numpy(tail))
+        bufs.append(t)
+        names.append(name + "+tail_error")
+        expected.append(s + n - 64)
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.time() - t0:.1f}s: {len(bufs)} x {n} bytes")
+
+    # correctness gate (the oracle checks are in tests/; here the generator's known answers)
+    for name, t, e in zip(names, bufs, expected):
+        got = u8.first_error(t)
+        if e is not None and got != e:
+            raise SystemExit(f"wrong result on {name}: {got} != {e}")
+        if e is None and name != "random" and got != -1:
+            raise SystemExit(f"wrong result on {name}: {got} != -1")
+
+    out = torch.empty(len(bufs), dtype=torch.int64, device=dev)
+    ptrs = [t.data_ptr() for t in bufs]
+    outp = [out.data_ptr() + 8 * i for i in range(len(bufs))]
+    validate_async = lib.utf8v_validate_async
+
+    def step(events=None):
+        for i, p in enumerate(ptrs):
+            if events is not None:
+                events[i][0].record(stream)
+            rc = validate_async(p, n, outp[i], sh)
+            if events is not None:
+                events[i][1].record(stream)
+            if rc:
+                raise u8.Utf8vError(rc, "utf8v_validate_async")
+
+    # ---- read ceiling on the same buffers -------------------------------------------------
+    ro = torch.zeros(1, dtype=torch.int32, device=dev)
+    for _ in range(2):
+        for t in bufs[:5]:
+            u8.read_ceiling(t, ro)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = 5
+    ev[0].record(stream)
+    for _ in range(reps):
+        for t in bufs[:5]:
+            u8.read_ceiling(t, ro)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    read_gbps = reps * 5 * n / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9
+
+    # ---- headline: K timed steps ----------------------------------------------------------
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+            for _ in bufs] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    res = out.cpu().numpy()
+    for name, e, r in zip(names, expected, res):
+        if e is not None and r != e:
+            raise SystemExit(f"wrong timed result on {name}")
+    per = np.array([[evs[k][i][0].elapsed_time(evs[k][i][1]) for i in range(len(bufs))]
+                    for k in range(args.steps)]) * 1e-3          # seconds
+    total_bytes = args.steps * len(bufs) * n
+    value = total_bytes / wall / 1e9
+    avg_launch = float(per.mean())
+    achieved = n / avg_launch / 1e9
+    per_variant = {names[i]: round(n / float(np.median(per[:, i])) / 1e9, 1) for i in range(len(bufs))}
+    log("per-variant GB/s:", per_variant, "read ceiling GB/s:", round(read_gbps, 1))
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "single-buffer validate, 1 GiB x (ascii, latin, cjk, emoji, random "
+                               "+ 4 copies with an error in the last 4 bytes) per step",
+                   "bytes_per_buffer": n, "buffers_per_step": len(bufs),
+                   "launch": u8.get_config()},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "kernel": "single_main (+ single_finalize) per 1 GiB launch, HIP events"},
+        "pct_hbm_peak": round(100 * value / HBM_PEAK_GBPS, 1),
+        "read_ceiling_GBps": round(read_gbps, 1),
+        "pct_of_read_ceiling": round(100 * value / read_gbps, 1),
+        "per_variant_GBps": per_variant,
+        "GiBps": round(total_bytes / wall / GIB, 1),
+    }
+
+    # ---- batched: 1M log-normal strings vs one launch per string ------------------------------
+    if not args.no_batch:
+        result["batched"] = bench_batch(u8, lib, synth, torch, dev, stream, sh, args)
+
+    # ---- CPU oracle on a bounded sample (1 core, as the paper's single thread) -----------------
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(host, n, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+def bench_batch(u8, lib, synth, torch, dev, stream, sh, args):
+    t0 = time.time()
+    data, offsets, expected = synth.lognormal_batch(args.batch_strings, 2)
+    td = torch.from_numpy(data).to(dev)
+    to = torch.from_numpy(offsets).to(dev)
+    flags = torch.empty(args.batch_strings, dtype=torch.uint8, device=dev)
+    ferr = torch.empty(args.batch_strings, dtype=torch.int64, device=dev)
+    log(f"batch inputs ready in {time.time() - t0:.1f}s: {data.size} bytes")
+    fn = lib.utf8v_validate_batch_async
+    nstr = args.batch_strings
+
+    def run():
+        rc = fn(td.data_ptr(), to.data_ptr(), nstr, flags.data_ptr(), ferr.data_ptr(), sh)
+        if rc:
+            raise u8.Utf8vError(rc, "utf8v_validate_batch_async")
+
+    for _ in range(3):
+        run()
+    torch.cuda.synchronize()
+    got = ferr.cpu().numpy()
+    if not np.array_equal(got[expected >= 0], expected[expected >= 0]) or (got[expected < 0] != -1).any():
+        raise SystemExit("wrong batch result")
+    reps = max(5, args.steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    warm = e0.elapsed_time(e1) * 1e-3 / reps
+    # cold: evict the MALL with a 1 GiB read between timed runs
+    scratch = torch.empty(GIB, dtype=torch.uint8, device=dev)
+    ro = torch.zeros(1, dtype=torch.int32, device=dev)
+    cold = []
+    for _ in range(5):
+        u8.read_ceiling(scratch, ro)
+        e0.record(stream)
+        run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        cold.append(e0.elapsed_time(e1) * 1e-3)
+    cold_t = float(np.median(cold))
+    del scratch
+    # baseline: one synchronous-free launch per string (validate_async per string), 10k subsample
+    sub = 10_000
+    outs = torch.empty(sub, dtype=torch.int64, device=dev)
+    va = lib.utf8v_validate_async
+    base = td.data_ptr()
+    offs = offsets[:sub + 1]
+    op = outs.data_ptr()
+    for k in range(200):
+        va(base + int(offs[k]), int(offs[k + 1] - offs[k]), op + 8 * k, sh)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(sub):
+        va(base + int(offs[k]), int(offs[k + 1] - offs[k]), op + 8 * k, sh)
+    torch.cuda.synchronize()
+    per_string = sub / (time.perf_counter() - t0)
+    if not np.array_equal(outs.cpu().numpy(), expected[:sub]):
+        raise SystemExit("wrong per-string result")
+    payload = int(offsets[-1] - offsets[0])
+    algo = payload + 17 * nstr   # payload + offsets (8 B) + flag (1 B) + first_err (8 B) per string
+    return {"workload": "1,000,000 strings, log-normal lengths (median 64 B, sigma 1.2, 1 B..64 KiB), "
+                        "mixed code points, 1% injected errors",
+            "strings_per_s_warm": round(nstr / warm), "strings_per_s_cold": round(nstr / cold_t),
+            "ms_warm": round(warm * 1e3, 3), "ms_cold": round(cold_t * 1e3, 3),
+            "payload_GBps_warm": round(payload / warm / 1e9, 1),
+            "algorithmic_GBps_warm": round(algo / warm / 1e9, 1),
+            "per_string_launch_strings_per_s": round(per_string),
+            "speedup_vs_per_string_launch": round(nstr / warm / per_string, 1)}
+
+
+def cpu_baseline(host, n, seconds):
+    """The oracle, single-threaded (the paper's protocol), on bounded prefixes of the valid variants.
+
+    The random-bytes variant is reported apart: the branchy walk stops at its
+    first error a few bytes in, while the GPU scans the whole buffer.
+    """
+    import oracle
+    per_variant = {}
+    total_b, total_t = 0, 0.0
+    valid = [k for k in host if k != "random"]
+    budget = seconds / len(valid)
+    for name in valid:
+        h = host[name]
+        size = 1 << 24
+        done_b, done_t = 0, 0.0
+        while done_t < budget and done_b < n:
+            seg = h[done_b: done_b + size]
+            t0 = time.perf_counter()
+            oracle.first_error(seg)
+            done_t += time.perf_counter() - t0
+            done_b += seg.size
+        per_variant[name] = round(done_b / done_t / 1e9, 3)
+        total_b += done_b
+        total_t += done_t
+    t0 = time.perf_counter()
+    r = oracle.first_error(host["random"])
+    per_variant["random(stops at offset %d)" % r] = round(n / (time.perf_counter() - t0) / 1e9, 1)
+    try:
+        cpu = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
+    except Exception:
+        cpu = platform.processor()
+    mib = total_b / len(valid) / (1 << 20)
+    return {"value": round(total_b / total_t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"branchy oracle on 1 thread over the first ~{mib:.0f} MiB of each valid variant buffer "
+                      f"(ascii, latin, cjk, emoji; 16 MiB segments, ~{budget:.1f} s each)",
+            "per_variant_GBps": per_variant, "host_cpu": cpu, "host_threads": os.cpu_count()}
+
+
+if __name__ == "__main__":
+    main()
