@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bounded oracle sample time")
+    ap.add_argument("--variants", default="ascii,latin,cjk,emoji,random",
+                    help="comma list of single-buffer variants (profiling runs restrict this)")
+    ap.add_argument("--no-tail-copies", action="store_true", help="skip the copies with a tail error")
+    ap.add_argument("--config", default="", help="launch overrides, e.g. unroll=4,waves_per_cu=24,ascii=1")
     return ap.parse_args()
 
 
@@ -67,6 +71,8 @@ def main():
     import paper_2010_03090_amd as u8
     from paper_2010_03090_amd import synth
     lib = u8.load()
+    if args.config:
+        u8.set_config(**{k: int(v) for k, v in (kv.split("=") for kv in args.config.split(","))})
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream or None
@@ -76,13 +82,14 @@ def main():
     t0 = time.time()
     bufs, names, expected = [], [], []
     host = {}
-    for name, seed in VARIANTS:
+    chosen = [v for v in VARIANTS if v[0] in args.variants.split(",")]
+    for name, seed in chosen:
         h = synth.text(n, name, seed)
         host[name] = h
         bufs.append(torch.from_numpy(h).to(dev))
         names.append(name)
         expected.append(None)
-    for name, seed in VARIANTS[:4]:
+    for name, seed in ([] if args.no_tail_copies else [v for v in chosen if v[0] != "random"]):
         t = bufs[names.index(name)].clone()
         tail, s, cls = synth.tail_error_copy(host[name][-64:], seed)
         t[-64:].copy_(torch.from_numpy(tail))
@@ -117,19 +124,20 @@ def main():
 
     # ---- read ceiling on the same buffers -------------------------------------------------
     ro = torch.zeros(1, dtype=torch.int32, device=dev)
+    base_bufs = bufs[:len(chosen)]
     for _ in range(2):
-        for t in bufs[:5]:
+        for t in base_bufs:
             u8.read_ceiling(t, ro)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     reps = 5
     ev[0].record(stream)
     for _ in range(reps):
-        for t in bufs[:5]:
+        for t in base_bufs:
             u8.read_ceiling(t, ro)
     ev[1].record(stream)
     torch.cuda.synchronize()
-    read_gbps = reps * 5 * n / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9
+    read_gbps = reps * len(base_bufs) * n / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9
 
     # ---- headline: K timed steps ----------------------------------------------------------
     for _ in range(args.warmup):
@@ -169,8 +177,9 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": "single-buffer validate, 1 GiB x (ascii, latin, cjk, emoji, random "
-                               "+ 4 copies with an error in the last 4 bytes) per step",
+        "config": {"workload": "single-buffer validate, 1 GiB x (" + ", ".join(v for v, _ in chosen) + ")"
+                               + ("" if args.no_tail_copies else " + copies with an error in the last 4 bytes")
+                               + " per step",
                    "bytes_per_buffer": n, "buffers_per_step": len(bufs),
                    "launch": u8.get_config()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -188,7 +197,7 @@ def main():
         result["batched"] = bench_batch(u8, lib, synth, torch, dev, stream, sh, args)
 
     # ---- CPU oracle on a bounded sample (1 core, as the paper's single thread) -----------------
-    if not args.no_cpu:
+    if not args.no_cpu and "random" in host and len(host) > 1:
         result["cpu_baseline"] = cpu_baseline(host, n, args.cpu_seconds)
     print(json.dumps(result), flush=True)
 

@@ -17,7 +17,7 @@ thread_local int g_last_status = UTF8V_OK;
 thread_local int g_last_hip = 0;
 
 std::mutex g_mu;
-utf8v_config g_cfg = {4, 16, 1, 4, 1};
+utf8v_config g_cfg = {4, 24, 1, 4, 1};
 
 struct Workspace {
   unsigned long long* dmin = nullptr;  // device: first detection position (kNone = none)

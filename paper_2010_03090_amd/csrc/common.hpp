@@ -11,7 +11,7 @@ constexpr int kDppWaveRor1 = 0x13C;               // DPP wave_ror:1 -- lane l re
 
 struct TuneSingle {
   int unroll = 4;             // dwordx4 loads in flight per lane (1 KiB per wave each)
-  int waves_per_cu = 16;      // persistent grid: waves per compute unit
+  int waves_per_cu = 24;      // persistent waves per compute unit (large = one tile per wave)
   int min_tiles_per_wave = 1;
   int ascii = 1;              // section 6.4 fast path for all-ASCII slabs
 };
@@ -46,7 +46,8 @@ struct BatchArgs {
   int64_t* first_err;
 };
 
-// Wave minimum of v (kNone = none), then one atomicMin into *dst.
+// Wave minimum of v (kNone = none), then one atomicMin into *dst unless *dst is
+// already lower (on inputs with errors everywhere, most waves then skip the atomic).
 __device__ __forceinline__ void wave_min_to(unsigned long long* dst, uint64_t v, int lane) {
   if (__any(v != kNone)) {
 #pragma unroll
@@ -54,7 +55,8 @@ __device__ __forceinline__ void wave_min_to(unsigned long long* dst, uint64_t v,
       const uint64_t o = __shfl_xor((unsigned long long)v, off);
       v = o < v ? o : v;
     }
-    if (lane == 0) atomicMin(dst, (unsigned long long)v);
+    if (lane == 0 && v < __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMin(dst, (unsigned long long)v);
   }
 }
 

@@ -61,6 +61,7 @@ __device__ __forceinline__ uint32_t align(uint32_t hi, uint32_t lo, uint32_t byt
 __device__ __forceinline__ uint32_t ge_mask7(uint32_t v, uint32_t k) {
   return __builtin_amdgcn_lerp(v, k, 0u);
 }
+// v_bitop3_b32 truth tables (operands a, b, c stand for 0xF0, 0xCC, 0xAA).
 // (m & a) | (~m & b)
 __device__ __forceinline__ uint32_t select_bits(uint32_t m, uint32_t a, uint32_t b) {
   return __builtin_amdgcn_bitop3_b32(m, a, b, 0xCA);
@@ -72,21 +73,36 @@ __device__ __forceinline__ uint32_t and3(uint32_t a, uint32_t b, uint32_t c) {
 __device__ __forceinline__ uint32_t or_and(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0xA8);
 }
+// (a & b) | c
+__device__ __forceinline__ uint32_t and_or(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0xEA);
+}
+// acc | (a ^ b)
+__device__ __forceinline__ uint32_t or_xor(uint32_t acc, uint32_t a, uint32_t b) {
+  return __builtin_amdgcn_bitop3_b32(acc, a, b, 0xF6);
+}
 
-// Section 6.1: the classification byte of each position (AND of the three lookups).
-// prev1 holds the byte before each position, prev2 the byte two before.
-__device__ __forceinline__ uint32_t classify(uint32_t x, uint32_t prev1, uint32_t prev2) {
-  const uint32_t sh2 = (x >> 4) & 0x07070707u;       // high nibble of the byte, low 3 bits
-  const uint32_t sh1 = (prev1 >> 4) & 0x07070707u;   // high nibble of prev1, low 3 bits
-  const uint32_t sl1 = prev1 & 0x07070707u;          // low nibble of prev1, low 3 bits
-  const uint32_t neg2 = perm(x, prev1, kSignSel);      // 0xFF where byte >= 0x80 (high nibble >= 8)
-  const uint32_t neg1 = perm(prev1, prev2, kSignSel);  // 0xFF where prev1 >= 0x80
-  // bit 3 of prev1's low nibble selects the byte_1_low half: byte k reads pool byte k or 4+k
-  const uint32_t half = ((prev1 >> 1) & 0x04040404u) | 0x03020100u;
+// The three table lookups of section 6.1 from prepared indices:
+//   sh1 / sl1 / sh2: low 3 bits of prev1's high nibble, prev1's low nibble, the byte's high nibble;
+//   neg1 / neg2:     0xFF where prev1 / the byte is >= 0x80 (bit 3 of the high nibble);
+//   half:            byte k = k + 4 * (bit 3 of prev1's low nibble).
+__device__ __forceinline__ uint32_t lookup3(uint32_t sh1, uint32_t sl1, uint32_t sh2, uint32_t neg1, uint32_t neg2,
+                                            uint32_t half) {
   const uint32_t byte_1_high = select_bits(neg1, perm(kB1H_HI_HI, kB1H_HI_LO, sh1), kB1H_LOW_HALF);
   const uint32_t byte_1_low = perm(perm(kB1L_HI_HI, kB1L_HI_LO, sl1), perm(kB1L_LO_HI, kB1L_LO_LO, sl1), half);
   const uint32_t byte_2_high = select_bits(neg2, perm(kB2H_HI_HI, kB2H_HI_LO, sh2), kB2H_LOW_HALF);
   return and3(byte_1_high, byte_1_low, byte_2_high);
+}
+
+__device__ __forceinline__ uint32_t low_half_selector(uint32_t prev1) {
+  return and_or(prev1 >> 1, 0x04040404u, 0x03020100u);
+}
+
+// Section 6.1: the classification byte of each position (AND of the three lookups).
+// prev1 holds the byte before each position, prev2 the byte two before.
+__device__ __forceinline__ uint32_t classify(uint32_t x, uint32_t prev1, uint32_t prev2) {
+  return lookup3((prev1 >> 4) & 0x07070707u, prev1 & 0x07070707u, (x >> 4) & 0x07070707u,
+                 perm(prev1, prev2, kSignSel), perm(x, prev1, kSignSel), low_half_selector(prev1));
 }
 
 // Section 6.2: 0x80 where a second continuation byte is required.
@@ -110,6 +126,56 @@ __device__ __forceinline__ uint32_t open_at_end(uint32_t p) {
   const uint32_t e = ge_mask7(p, 0x20202020u) & 0x00800000u;  // byte 2 >= 0xE0
   const uint32_t f = ge_mask7(p, 0x10101010u) & 0x00008000u;  // byte 1 >= 0xF0
   return c | e | f;
+}
+
+// ---- a run of consecutive registers ----------------------------------------------------
+// Along a run, the sign masks, high-nibble indices and must23 inputs of a register
+// are computed once and shifted in for the next register instead of being
+// recomputed from the shifted bytes.
+
+struct Carry {
+  uint32_t neg2;  // sign mask of the bytes
+  uint32_t sh2;   // low 3 bits of the high nibbles
+  uint32_t g;     // bit 7 at byte j: b[j] >= 0xE0 or b[j-1] >= 0xF0
+};
+
+// Errors of the first register x of a run, preceded by p, ORed into acc; fills c for x.
+__device__ __forceinline__ uint32_t errors_first(uint32_t acc, uint32_t x, uint32_t p, Carry& c) {
+  const uint32_t prev1 = align(x, p, 3);
+  const uint32_t prev2 = align(x, p, 2);
+  const uint32_t prev3 = align(x, p, 1);
+  c.neg2 = perm(x, prev1, kSignSel);
+  c.sh2 = (x >> 4) & 0x07070707u;
+  c.g = or_and(ge_mask7(x, 0x20202020u), ge_mask7(prev1, 0x10101010u), 0x80808080u);
+  const uint32_t sc = lookup3((prev1 >> 4) & 0x07070707u, prev1 & 0x07070707u, c.sh2, perm(prev1, prev2, kSignSel),
+                              c.neg2, low_half_selector(prev1));
+  return or_xor(acc, sc, must23(prev2, prev3));
+}
+
+// Errors of register x following register xp in the run, ORed into acc (c holds xp's
+// values; updated to x's).  must23 at position i equals g at position i-2.
+__device__ __forceinline__ uint32_t errors_next(uint32_t acc, uint32_t x, uint32_t xp, Carry& c) {
+  const uint32_t prev1 = align(x, xp, 3);
+  const uint32_t neg2 = perm(x, prev1, kSignSel);
+  const uint32_t sh2 = (x >> 4) & 0x07070707u;
+  const uint32_t g = or_and(ge_mask7(x, 0x20202020u), ge_mask7(prev1, 0x10101010u), 0x80808080u);
+  const uint32_t sc = lookup3(align(sh2, c.sh2, 3), prev1 & 0x07070707u, sh2, align(neg2, c.neg2, 3), neg2,
+                              low_half_selector(prev1));
+  acc = or_xor(acc, sc, align(g, c.g, 2));
+  c.neg2 = neg2;
+  c.sh2 = sh2;
+  c.g = g;
+  return acc;
+}
+
+// Errors of a 16-byte chunk (x0..x3) preceded by the dword p, ORed into acc.
+__device__ __forceinline__ uint32_t chunk_errors(uint32_t acc, uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                                 uint32_t p) {
+  Carry c;
+  acc = errors_first(acc, x0, p, c);
+  acc = errors_next(acc, x1, x0, c);
+  acc = errors_next(acc, x2, x1, c);
+  return errors_next(acc, x3, x2, c);
 }
 
 // Index (0..3) of the lowest non-zero byte of a non-zero register.

@@ -34,19 +34,36 @@ hipError_t launch_classify(const uint8_t* buf, uint64_t n, uint8_t* sc, uint8_t*
   return hipGetLastError();
 }
 
-// Read ceiling: OR of all 16-byte words of a 16-byte aligned buffer (n multiple of 16).
-__global__ __launch_bounds__(256) void read_or(const uint4* __restrict__ p, uint64_t words, uint32_t* out) {
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Read ceiling: every wave reads one 4 KiB tile (four 1 KiB slabs, one
+// non-temporal dwordx4 per lane each) and ORs it -- the load pattern of the
+// validator without its arithmetic.  Words past the last whole tile are read
+// by block 0.  n is a multiple of 16.
+__global__ __launch_bounds__(256) void read_or(const uint8_t* __restrict__ buf, uint64_t n, uint32_t* out) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t wave = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint64_t tiles = n / 4096;
   uint32_t acc = 0;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i + 3 * stride < words; i += 4 * stride) {
-    const uint4 a = p[i], b = p[i + stride], c = p[i + 2 * stride], d = p[i + 3 * stride];
-    acc |= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^ d.z ^ d.w;
+  if (wave < tiles) {
+    const uint8_t* b = buf + wave * 4096 + lane * 16;
+    u32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(b + u * 1024));
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc |= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
   }
-  for (; i < words; i += stride) { const uint4 a = p[i]; acc |= a.x ^ a.y ^ a.z ^ a.w; }
+  if (blockIdx.x == 0) {
+    for (uint64_t i = tiles * 4096 + (uint64_t)threadIdx.x * 16; i < n; i += 256 * 16) {
+      const u32x4 v = *reinterpret_cast<const u32x4*>(buf + i);
+      acc |= v.x ^ v.y ^ v.z ^ v.w;
+    }
+  }
   if (__any(acc != 0)) {
     for (int off = 32; off > 0; off >>= 1) acc |= __shfl_xor(acc, off);
-    if ((threadIdx.x & 63) == 0 && acc) atomicOr(out, acc);
+    // only bits not yet set need the atomic (keeps a million waves off one address)
+    if (lane == 0 && (acc & ~__hip_atomic_load(out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0)
+      atomicOr(out, acc);
   }
 }
 
@@ -56,8 +73,10 @@ __global__ __launch_bounds__(256) void copy16(const uint4* __restrict__ s, uint4
 }
 
 hipError_t launch_read_ceiling(const uint8_t* buf, uint64_t n, uint32_t* out, int num_cus, hipStream_t st) {
-  hipLaunchKernelGGL(read_or, dim3((unsigned)(num_cus * 8)), dim3(256), 0, st,
-                     reinterpret_cast<const uint4*>(buf), n / 16, out);
+  (void)num_cus;
+  const uint64_t waves = n / 4096;
+  const unsigned blocks = (unsigned)((waves + 3) / 4 > 0 ? (waves + 3) / 4 : 1);
+  hipLaunchKernelGGL(read_or, dim3(blocks), dim3(256), 0, st, buf, n, out);
   return hipGetLastError();
 }
 

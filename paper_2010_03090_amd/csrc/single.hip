@@ -12,6 +12,8 @@
 // section 6.1) come from the neighbouring lane through DPP (wave_ror:1); lane 0
 // takes the last dword of the previous slab, and the first slab of a wave's
 // first tile reads it from memory (zero before the buffer start, section 6).
+// Inside a chunk the four dwords form a run: sign masks, nibble indices and the
+// section 6.2 inputs of one dword are shifted into the next (errors_next).
 //
 // Errors are ORed into a per-lane register (section 6, "error register").  Only
 // when it is non-zero does a lane recompute its chunk to find its first
@@ -32,47 +34,71 @@ __device__ __forceinline__ uint32_t prev_dword(const uint8_t* __restrict__ buf, 
   return v;
 }
 
-template <int U, bool ASCII, bool FULL>
-__device__ __forceinline__ void single_tile(const uint8_t* __restrict__ buf, uint64_t base, uint64_t i1, int lane,
-                                            uint32_t& carry, uint64_t& dmin) {
-  uint4 x[U];
-  bool live[U];
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kAsciiBackoff = 3;
+
+// Streaming 16-byte load; non-temporal, the input is read exactly once.
+__device__ __forceinline__ u32x4 load16(const uint8_t* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+}
+
+template <int U, bool FULL>
+__device__ __forceinline__ void load_tile(u32x4 (&x)[U], const uint8_t* __restrict__ buf, uint64_t base,
+                                          uint64_t i1, int lane) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const uint64_t pos = base + (uint64_t)u * 1024 + (uint64_t)lane * 16;
-    live[u] = FULL || pos < i1;
-    if (FULL || live[u]) x[u] = *reinterpret_cast<const uint4*>(buf + pos);
-    else x[u] = make_uint4(0, 0, 0, 0);
+    x[u] = (FULL || pos < i1) ? load16(buf + pos) : u32x4{0, 0, 0, 0};
   }
+}
+
+// Validate one wave tile already in registers.  `carry` (lane 0) holds the dword
+// before the tile and leaves with the tile's last dword.
+template <int U, bool ASCII, bool FULL>
+__device__ __forceinline__ void single_tile(const u32x4 (&x)[U], uint64_t base, uint64_t i1, int lane,
+                                            uint32_t& carry, uint64_t& dmin, int& ascii_skip) {
+  // previous dword of each chunk: lane l-1's last dword (lane 0: lane 63 of the previous slab)
   uint32_t prev[U];
-  uint32_t acc = 0;
   const bool lane0 = lane == 0;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    // previous dword: lane l-1's last dword; lane 0 gets the previous slab's lane 63
-    const uint32_t rot = __builtin_amdgcn_update_dpp(0u, x[u].w, kDppWaveRor1, 0xF, 0xF, false);
+    const uint32_t rot = (uint32_t)__builtin_amdgcn_mov_dpp((int)x[u].w, kDppWaveRor1, 0xF, 0xF, true);
     prev[u] = lane0 ? carry : rot;
     carry = rot;  // lane 0 now holds lane 63's last dword of this slab
-    if (ASCII) {
-      // Section 6.4: when the slab and the three bytes before it are all ASCII,
-      // no check can fire in it (an ASCII byte after ASCII bytes is never an
-      // error), so the classification is skipped for the whole wave.
-      const uint32_t hi = (x[u].x | x[u].y | x[u].z | x[u].w | prev[u]) & 0x80808080u;
-      if (__all(hi == 0)) continue;
+  }
+  if (ASCII) {
+    // Section 6.4: when the tile and the three bytes before it are all ASCII, no
+    // check can fire in it (an ASCII byte after ASCII bytes is never an error).
+    // After a tile that is not all ASCII the wave skips the test for the next
+    // kAsciiBackoff tiles, so text without long ASCII runs barely pays for it.
+    if (ascii_skip == 0) {
+      uint32_t o = 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) o |= x[u].x | x[u].y | x[u].z | x[u].w | prev[u];
+      if (__all((o & 0x80808080u) == 0)) return;
+      ascii_skip = kAsciiBackoff;
+    } else {
+      --ascii_skip;
     }
-    uint32_t e = position_errors(x[u].x, prev[u]);
-    e |= position_errors(x[u].y, x[u].x);
-    e |= position_errors(x[u].z, x[u].y);
-    e |= position_errors(x[u].w, x[u].z);
-    acc |= (FULL || live[u]) ? e : 0u;
+  }
+  uint32_t acc = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (FULL) {
+      acc = chunk_errors(acc, x[u].x, x[u].y, x[u].z, x[u].w, prev[u]);
+    } else {
+      const uint32_t e = chunk_errors(0u, x[u].x, x[u].y, x[u].z, x[u].w, prev[u]);
+      acc |= (base + (uint64_t)u * 1024 + (uint64_t)lane * 16 < i1) ? e : 0u;
+    }
   }
   if (__builtin_expect(acc != 0, 0) && dmin == kNone) {
     // first detection position of this lane (exact recomputation, rare)
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (!(FULL || live[u])) continue;
-      const uint32_t w[5] = {prev[u], x[u].x, x[u].y, x[u].z, x[u].w};
       const uint64_t pos = base + (uint64_t)u * 1024 + (uint64_t)lane * 16;
+      if (!FULL && pos >= i1) continue;
+      const uint32_t w[5] = {prev[u], x[u].x, x[u].y, x[u].z, x[u].w};
       for (int j = 0; j < 4; ++j) {
         const uint32_t e = position_errors(w[j + 1], w[j]);
         if (e && dmin == kNone) dmin = pos + 4 * j + first_byte(e);
@@ -82,6 +108,8 @@ __device__ __forceinline__ void single_tile(const uint8_t* __restrict__ buf, uin
   }
 }
 
+// One wave takes a contiguous run of tiles; the loads of tile t+1 are issued
+// before tile t is classified, so memory and the VALU work overlap in each wave.
 template <int U, bool ASCII>
 __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
   const int lane = threadIdx.x & 63;
@@ -91,11 +119,29 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
   const uint64_t t_end = t + a.tiles_per_wave < a.tiles ? t + a.tiles_per_wave : a.tiles;
   if (t >= t_end) return;
   uint64_t dmin = kNone;
+  int ascii_skip = 0;
   uint32_t carry = prev_dword(a.buf, a.i0 + t * W);
-  for (; t < t_end; ++t) {
-    const uint64_t base = a.i0 + t * W;
-    if (base + W <= a.i1) single_tile<U, ASCII, true>(a.buf, base, a.i1, lane, carry, dmin);
-    else single_tile<U, ASCII, false>(a.buf, base, a.i1, lane, carry, dmin);
+  // the buffer's last tile may be partial
+  const uint64_t t_full = (t_end == a.tiles && a.i0 + a.tiles * W > a.i1) ? t_end - 1 : t_end;
+  if (t < t_full) {
+    // two register sets in turn: one is classified while the other's loads are in flight
+    u32x4 xa[U], xb[U];
+    load_tile<U, true>(xa, a.buf, a.i0 + t * W, a.i1, lane);
+    for (; t + 1 < t_full; t += 2) {
+      load_tile<U, true>(xb, a.buf, a.i0 + (t + 1) * W, a.i1, lane);
+      single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii_skip);
+      if (t + 2 < t_full) load_tile<U, true>(xa, a.buf, a.i0 + (t + 2) * W, a.i1, lane);
+      single_tile<U, ASCII, true>(xb, a.i0 + (t + 1) * W, a.i1, lane, carry, dmin, ascii_skip);
+    }
+    if (t < t_full) {
+      single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii_skip);
+      ++t;
+    }
+  }
+  if (t < t_end) {
+    u32x4 x[U];
+    load_tile<U, false>(x, a.buf, a.i0 + t * W, a.i1, lane);
+    single_tile<U, ASCII, false>(x, a.i0 + t * W, a.i1, lane, carry, dmin, ascii_skip);
   }
   wave_min_to(a.dmin, dmin, lane);
 }
