@@ -45,6 +45,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup-seconds", type=float, default=0.5,
+                    help="keep warming up until this much time passed (engine clocks ramp up under load)")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-buffer part (batch profiling)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also copy one buffer (profiling: scales the HBM traffic counters)")
+    ap.add_argument("--per-string", type=int, default=10_000,
+                    help="strings in the one-launch-per-string baseline (0 skips it)")
     ap.add_argument("--size", type=int, default=GIB, help="bytes per single buffer")
     ap.add_argument("--batch-strings", type=int, default=1_000_000)
     ap.add_argument("--no-batch", action="store_true")
@@ -77,6 +84,23 @@ def main():
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream or None
 
+    if args.no_single:
+        result = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "data": "synthetic"}
+        host = {}
+    else:
+        result, host = bench_single(u8, lib, synth, torch, dev, stream, sh, args)
+
+    # ---- batched: 1M log-normal strings vs one launch per string ------------------------------
+    if not args.no_batch:
+        result["batched"] = bench_batch(u8, lib, synth, torch, dev, stream, sh, args)
+
+    # ---- CPU oracle on a bounded sample (1 core, as the paper's single thread) -----------------
+    if not args.no_cpu and "random" in host and len(host) > 1:
+        result["cpu_baseline"] = cpu_baseline(host, args.size, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+def bench_single(u8, lib, synth, torch, dev, stream, sh, args):
     # ---- inputs (generated on the host, copied to HBM before timing) ---------------------
     n = args.size
     t0 = time.time()
@@ -140,9 +164,12 @@ def main():
     read_gbps = reps * len(base_bufs) * n / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9
 
     # ---- headline: K timed steps ----------------------------------------------------------
-    for _ in range(args.warmup):
+    t_w = time.perf_counter()
+    done = 0
+    while done < args.warmup or time.perf_counter() - t_w < args.warmup_seconds:
         step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        done += 1
     evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
             for _ in bufs] for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -151,6 +178,12 @@ def main():
         step(evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if args.copy_probe:
+        dst = torch.empty_like(bufs[0])
+        for _ in range(3):
+            u8.copy(bufs[0], dst)
+        torch.cuda.synchronize()
+        del dst
     res = out.cpu().numpy()
     for name, e, r in zip(names, expected, res):
         if e is not None and r != e:
@@ -192,14 +225,7 @@ def main():
         "GiBps": round(total_bytes / wall / GIB, 1),
     }
 
-    # ---- batched: 1M log-normal strings vs one launch per string ------------------------------
-    if not args.no_batch:
-        result["batched"] = bench_batch(u8, lib, synth, torch, dev, stream, sh, args)
-
-    # ---- CPU oracle on a bounded sample (1 core, as the paper's single thread) -----------------
-    if not args.no_cpu and "random" in host and len(host) > 1:
-        result["cpu_baseline"] = cpu_baseline(host, n, args.cpu_seconds)
-    print(json.dumps(result), flush=True)
+    return result, host
 
 
 def bench_batch(u8, lib, synth, torch, dev, stream, sh, args):
@@ -218,9 +244,10 @@ def bench_batch(u8, lib, synth, torch, dev, stream, sh, args):
         if rc:
             raise u8.Utf8vError(rc, "utf8v_validate_batch_async")
 
-    for _ in range(3):
+    t_w = time.perf_counter()
+    while time.perf_counter() - t_w < args.warmup_seconds:
         run()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
     got = ferr.cpu().numpy()
     if not np.array_equal(got[expected >= 0], expected[expected >= 0]) or (got[expected < 0] != -1).any():
         raise SystemExit("wrong batch result")
@@ -245,23 +272,25 @@ def bench_batch(u8, lib, synth, torch, dev, stream, sh, args):
         cold.append(e0.elapsed_time(e1) * 1e-3)
     cold_t = float(np.median(cold))
     del scratch
-    # baseline: one synchronous-free launch per string (validate_async per string), 10k subsample
-    sub = 10_000
-    outs = torch.empty(sub, dtype=torch.int64, device=dev)
-    va = lib.utf8v_validate_async
-    base = td.data_ptr()
-    offs = offsets[:sub + 1]
-    op = outs.data_ptr()
-    for k in range(200):
-        va(base + int(offs[k]), int(offs[k + 1] - offs[k]), op + 8 * k, sh)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(sub):
-        va(base + int(offs[k]), int(offs[k + 1] - offs[k]), op + 8 * k, sh)
-    torch.cuda.synchronize()
-    per_string = sub / (time.perf_counter() - t0)
-    if not np.array_equal(outs.cpu().numpy(), expected[:sub]):
-        raise SystemExit("wrong per-string result")
+    # baseline: one launch per string (validate_async per string) on a subsample
+    sub = args.per_string
+    per_string = None
+    if sub > 0:
+        outs = torch.empty(sub, dtype=torch.int64, device=dev)
+        va = lib.utf8v_validate_async
+        base = td.data_ptr()
+        offs = offsets[:sub + 1]
+        op = outs.data_ptr()
+        for k in range(min(200, sub)):
+            va(base + int(offs[k]), int(offs[k + 1] - offs[k]), op + 8 * k, sh)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(sub):
+            va(base + int(offs[k]), int(offs[k + 1] - offs[k]), op + 8 * k, sh)
+        torch.cuda.synchronize()
+        per_string = sub / (time.perf_counter() - t0)
+        if not np.array_equal(outs.cpu().numpy(), expected[:sub]):
+            raise SystemExit("wrong per-string result")
     payload = int(offsets[-1] - offsets[0])
     algo = payload + 17 * nstr   # payload + offsets (8 B) + flag (1 B) + first_err (8 B) per string
     return {"workload": "1,000,000 strings, log-normal lengths (median 64 B, sigma 1.2, 1 B..64 KiB), "
@@ -270,8 +299,8 @@ def bench_batch(u8, lib, synth, torch, dev, stream, sh, args):
             "ms_warm": round(warm * 1e3, 3), "ms_cold": round(cold_t * 1e3, 3),
             "payload_GBps_warm": round(payload / warm / 1e9, 1),
             "algorithmic_GBps_warm": round(algo / warm / 1e9, 1),
-            "per_string_launch_strings_per_s": round(per_string),
-            "speedup_vs_per_string_launch": round(nstr / warm / per_string, 1)}
+            "per_string_launch_strings_per_s": round(per_string) if per_string else None,
+            "speedup_vs_per_string_launch": round(nstr / warm / per_string, 1) if per_string else None}
 
 
 def cpu_baseline(host, n, seconds):

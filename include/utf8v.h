@@ -101,8 +101,8 @@ typedef struct {
   int32_t unroll;            /* single buffer: dwordx4 loads per lane per tile, 1, 2, 4 or 8 */
   int32_t waves_per_cu;      /* single buffer: persistent waves per compute unit, >= 1 */
   int32_t ascii;             /* 1: skip classification of all-ASCII 1 KiB slabs (section 6.4) */
-  int32_t batch_blocks_per_cu; /* batch: persistent 256-thread blocks per compute unit, >= 1 */
-  int32_t batch_ascii;       /* batch: 1 = ASCII skip per wave chunk */
+  int32_t batch_waves_per_cu; /* batch: persistent one-wave workgroups per compute unit, 1..64 */
+  int32_t batch_ascii;       /* reserved (the batch kernel always uses the section 6.4 skip) */
 } utf8v_config;
 
 /* Read / replace the launch configuration of the calling process (all devices). */

@@ -17,7 +17,7 @@ thread_local int g_last_status = UTF8V_OK;
 thread_local int g_last_hip = 0;
 
 std::mutex g_mu;
-utf8v_config g_cfg = {4, 24, 1, 4, 1};
+utf8v_config g_cfg = {4, 24, 1, 16, 1};
 
 struct Workspace {
   unsigned long long* dmin = nullptr;  // device: first detection position (kNone = none)
@@ -109,7 +109,7 @@ utf8v::TuneSingle tune_single() {
 utf8v::TuneBatch tune_batch() {
   std::lock_guard<std::mutex> lk(g_mu);
   utf8v::TuneBatch t;
-  t.blocks_per_cu = g_cfg.batch_blocks_per_cu;
+  t.waves_per_cu = g_cfg.batch_waves_per_cu;
   t.ascii = g_cfg.batch_ascii;
   return t;
 }
@@ -221,7 +221,7 @@ int utf8v_set_config(const utf8v_config* cfg) {
   if (!cfg) return set_status(UTF8V_EINVAL);
   const bool ok = (cfg->unroll == 1 || cfg->unroll == 2 || cfg->unroll == 4 || cfg->unroll == 8) &&
                   cfg->waves_per_cu >= 1 && cfg->waves_per_cu <= 4096 && (cfg->ascii == 0 || cfg->ascii == 1) &&
-                  cfg->batch_blocks_per_cu >= 1 && cfg->batch_blocks_per_cu <= 64 &&
+                  cfg->batch_waves_per_cu >= 1 && cfg->batch_waves_per_cu <= 64 &&
                   (cfg->batch_ascii == 0 || cfg->batch_ascii == 1);
   if (!ok) return set_status(UTF8V_EINVAL);
   std::lock_guard<std::mutex> lk(g_mu);

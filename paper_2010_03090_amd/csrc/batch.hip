@@ -26,9 +26,12 @@
 
 namespace utf8v {
 
-constexpr int kTile = 4096;                 // bytes per tile (256 lanes x 16 bytes)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kU = 4;                       // 1 KiB slabs per wave tile
+constexpr int kTile = kU * 1024;            // bytes per tile (one wave)
 constexpr int kMaskPad = 16;                // mask bytes kept before the tile (last 4 used)
-constexpr int kOffCap = 1024;               // tile boundaries cached in LDS for the error path
+constexpr int kOffCap = 128;                // window boundaries cached in LDS for the error path
 
 __global__ void batch_init(int64_t* tmp, int64_t n) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
@@ -36,180 +39,221 @@ __global__ void batch_init(int64_t* tmp, int64_t n) {
 }
 
 // First k in [0, n] with offsets[k] >= target (offsets[n] >= target is guaranteed by the caller).
-__device__ int64_t block_lower_bound(const int64_t* __restrict__ offsets, int64_t n, int64_t target, int tid) {
+__device__ int64_t wave_lower_bound(const int64_t* __restrict__ offsets, int64_t n, int64_t target, int lane) {
   int64_t lo = 0, hi = n;  // answer in [lo, hi]
   while (lo < hi) {
-    const int64_t span = hi - lo;
-    const int64_t step = (span + 255) / 256;
-    const int64_t idx = lo + (int64_t)tid * step;
+    const int64_t step = (hi - lo + 63) / 64;
+    const int64_t idx = lo + (int64_t)lane * step;
     const bool below = idx < hi && offsets[idx] < target;
-    const int c = __syncthreads_count(below);
+    const int c = __popcll(__ballot(below));
     const int64_t new_lo = c == 0 ? lo : lo + (int64_t)(c - 1) * step + 1;
     int64_t new_hi = lo + (int64_t)c * step;
-    if (new_hi > hi) new_hi = hi;
     lo = new_lo;
-    hi = new_hi;
+    hi = new_hi < hi ? new_hi : hi;
   }
   return lo;
 }
 
-// String holding position pos: the last k with offsets[k] <= pos (offsets[k0-1] < window start).
+// String holding position pos: the last k in [k0-1, k1-1] with offsets[k] <= pos.
+// Boundaries k0..k1-1 are cached in LDS (soff) when there are at most kOffCap of them.
 __device__ int64_t string_of(int64_t pos, const int64_t* __restrict__ offsets, int64_t k0, int64_t k1,
-                             const int64_t* lds_off) {
-  int64_t lo = k0, hi = k1;  // first k in [k0, k1] with offsets[k] > pos
+                             const int64_t* soff) {
   const bool cached = k1 - k0 <= kOffCap;
+  int64_t lo = k0, hi = k1;  // first k in [k0, k1] with offsets[k] > pos
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
-    const int64_t v = cached ? lds_off[mid - k0] : offsets[mid];
+    const int64_t v = cached ? soff[mid - k0] : offsets[mid];
     if (v <= pos) lo = mid + 1; else hi = mid;
   }
   return lo - 1;
 }
 
-// Lookup checks with per-string masking.  x: the chunk dword, p: the dword before it,
-// s / sp: string-start masks (0xFF where a string starts) of the same two dwords.
-// Returns the errors of the strings holding each position; *tail gets the end
-// check of the strings ending at each position.
-__device__ __forceinline__ uint32_t masked_errors(uint32_t x, uint32_t p, uint32_t s, uint32_t sp, uint32_t* tail) {
-  const uint32_t s1 = align(s, sp, 3);                     // position i-1 starts a string
-  const uint32_t s2 = align(s, sp, 2);                     // position i-2 starts a string
-  const uint32_t prev1 = align(x, p, 3);
-  const uint32_t prev2 = align(x, p, 2);
-  const uint32_t prev3 = align(x, p, 1);
-  const uint32_t r2 = s | s1;                              // byte i-2 is in another string
-  const uint32_t r3 = r2 | s2;                             // byte i-3 is in another string
-  const uint32_t p1m = prev1 & ~s;
-  // classification with prev1 of the same string (zero at a string start)
-  const uint32_t sh2 = (x >> 4) & 0x07070707u;
-  const uint32_t sh1 = (p1m >> 4) & 0x07070707u;
-  const uint32_t sl1 = p1m & 0x07070707u;
-  const uint32_t neg2 = perm(x, prev1, kSignSel);
-  const uint32_t neg1 = perm(p1m, p1m << 8, kSignSel);
-  const uint32_t half = ((p1m >> 1) & 0x04040404u) | 0x03020100u;
-  const uint32_t b1h = select_bits(neg1, perm(kB1H_HI_HI, kB1H_HI_LO, sh1), kB1H_LOW_HALF);
-  const uint32_t b1l = perm(perm(kB1L_HI_HI, kB1L_HI_LO, sl1), perm(kB1L_LO_HI, kB1L_LO_LO, sl1), half);
-  const uint32_t b2h = select_bits(neg2, perm(kB2H_HI_HI, kB2H_HI_LO, sh2), kB2H_LOW_HALF);
-  const uint32_t sc = and3(b1h, b1l, b2h);
-  const uint32_t ge_e0 = ge_mask7(prev2, 0x20202020u);     // bit 7: byte i-2 >= 0xE0
-  const uint32_t ge_f0 = ge_mask7(prev3, 0x10101010u);     // bit 7: byte i-3 >= 0xF0
-  const uint32_t ge_c0 = ge_mask7(prev1, 0x40404040u);     // bit 7: byte i-1 >= 0xC0
-  // section 6.2 within the string of position i
-  const uint32_t m23 = ((ge_e0 & ~r2) | (ge_f0 & ~r3)) & 0x80808080u;
-  // section 6.3 for the string ending at i (its bytes i-1, and i-2 / i-3 when they are its own)
-  *tail = (ge_c0 | (ge_e0 & ~s1) | (ge_f0 & ~(s1 | s2))) & s & 0x80808080u;
-  return sc ^ m23;
+// Bytes [q, q+4) of the batch range [lo, hi) as a dword, zero outside the range.
+__device__ uint32_t range_dword(const uint8_t* __restrict__ data, int64_t q, int64_t lo, int64_t hi) {
+  uint32_t v = 0;
+  for (int b = 0; b < 4; ++b)
+    if (q + b >= lo && q + b < hi) v |= (uint32_t)data[q + b] << (8 * b);
+  return v;
 }
 
-__global__ __launch_bounds__(256) void batch_main(BatchArgs a) {
-  __shared__ __align__(16) uint8_t smask[kTile + kMaskPad];
-  __shared__ int64_t lds_off[kOffCap];
-  const int tid = threadIdx.x;
+// 16-byte chunk at c (16-byte aligned address) with bytes outside [lo, hi) zeroed.  The
+// aligned 16 bytes are loaded only when one of them is in the range, so they lie in
+// a page that holds batch bytes.
+__device__ u32x4 edge_chunk(const uint8_t* __restrict__ data, int64_t c, int64_t lo, int64_t hi) {
+  if (c + 16 <= lo || c >= hi) return u32x4{0, 0, 0, 0};
+  u32x4 v = *reinterpret_cast<const u32x4*>(data + c);
+  uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  for (int j = 0; j < 4; ++j) {
+    const int64_t q = c + 4 * j;
+    int64_t a = lo - q, b = hi - q;  // keep bytes [a, b) of this dword
+    a = a < 0 ? 0 : (a > 4 ? 4 : a);
+    b = b < 0 ? 0 : (b > 4 ? 4 : b);
+    const uint64_t keep = b > a ? (((1ull << (8 * b)) - 1) & ~((1ull << (8 * a)) - 1)) : 0ull;
+    w[j] &= (uint32_t)keep;
+  }
+  return u32x4{w[0], w[1], w[2], w[3]};
+}
+
+__device__ __forceinline__ void note_error(int64_t* tmp, int64_t k, int64_t rel) {
+  atomicMin(reinterpret_cast<unsigned long long*>(tmp + k), (unsigned long long)rel);
+}
+
+// Start offset of string k, for k in [k0-1, k1-1] (LDS when cached).
+__device__ __forceinline__ int64_t string_start(int64_t k, const int64_t* __restrict__ offsets, int64_t k0, int64_t k1,
+                                                const int64_t* soff) {
+  return (k >= k0 && k1 - k0 <= kOffCap) ? soff[k - k0] : offsets[k];
+}
+
+// End offset of string k (the next boundary), for k in [k0-1, k1-1].
+__device__ __forceinline__ int64_t string_end(int64_t k, const int64_t* __restrict__ offsets, int64_t k0, int64_t k1,
+                                              const int64_t* soff) {
+  return (k + 1 < k1 && k1 - k0 <= kOffCap) ? soff[k + 1 - k0] : offsets[k + 1];
+}
+
+// Loads of one tile: interior tiles read whole chunks (non-temporal); tiles at the
+// edges of the batch range read through edge_chunk.
+__device__ __forceinline__ void batch_load(u32x4 (&x)[kU], const uint8_t* __restrict__ data, int64_t ts, int64_t lo,
+                                           int64_t hi, int lane) {
+  if (ts - 4 >= lo && ts + kTile <= hi) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      x[u] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(data + ts + u * 1024 + lane * 16));
+  } else {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) x[u] = edge_chunk(data, ts + u * 1024 + lane * 16, lo, hi);
+  }
+}
+
+// One wave per workgroup; each wave validates a contiguous run of 4 KiB tiles.  The
+// data and the first boundary offsets of tile t+1 are requested right after tile
+// t's boundary scan, before tile t is classified, so their latency overlaps it.
+__global__ __launch_bounds__(64) void batch_main(BatchArgs a) {
+  __shared__ __align__(16) uint8_t smask[kTile + kMaskPad];  // string starts at positions [ts-16, te)
+  __shared__ int64_t soff[kOffCap];                           // offsets[k0 ..] of the window
+  const int lane = threadIdx.x;
   const int64_t* __restrict__ offsets = a.offsets;
-  // The byte range is read on the device, so one launch shape serves any batch.
-  a.lo = offsets[0];
-  a.hi = offsets[a.n];
-  a.c0 = a.lo - (int64_t)((reinterpret_cast<uintptr_t>(a.data) + (uintptr_t)a.lo) & 15);
+  const uint8_t* __restrict__ data = a.data;
+  // the byte range is read on the device, so one launch shape serves any batch
+  const int64_t lo = offsets[0], hi = offsets[a.n];
+  const int64_t c0 = lo - (int64_t)((reinterpret_cast<uintptr_t>(data) + (uintptr_t)lo) & 15);
   // tiles cover [c0, hi]: position hi holds the end check of the last string
-  const int64_t tiles = (a.hi + 1 - a.c0 + kTile - 1) / kTile;
-  const int64_t per_block = (tiles + gridDim.x - 1) / gridDim.x;
-  int64_t t = (int64_t)blockIdx.x * per_block;
-  const int64_t t_end = t + per_block < tiles ? t + per_block : tiles;
+  const int64_t tiles = (hi + 1 - c0 + kTile - 1) / kTile;
+  const int64_t per = (tiles + gridDim.x - 1) / gridDim.x;
+  int64_t t = (int64_t)blockIdx.x * per;
+  const int64_t t_end = t + per < tiles ? t + per : tiles;
   if (t >= t_end) return;
-  // boundaries at or after the first tile's mask window
-  int64_t k0 = block_lower_bound(offsets, a.n, a.c0 + t * kTile - 4, tid);
+  int64_t k0 = wave_lower_bound(offsets, a.n, c0 + t * kTile - 4, lane);
+  uint32_t carry = range_dword(data, c0 + t * kTile - 4, lo, hi);  // the dword before the first tile
+  const bool lane0 = lane == 0;
+  int ascii_skip = 0;
+
+  u32x4 x[kU];
+  batch_load(x, data, c0 + t * kTile, lo, hi, lane);
+  int64_t v = k0 + lane <= a.n ? offsets[k0 + lane] : INT64_MAX;
 
   for (; t < t_end; ++t) {
-    const int64_t ts = a.c0 + t * kTile;                   // tile start position
+    const int64_t ts = c0 + t * kTile;
     const int64_t te = ts + kTile;
-    // 1. string-start mask for positions [ts - 4, te)
-    reinterpret_cast<uint4*>(smask)[tid] = make_uint4(0, 0, 0, 0);
-    if (tid == 0) reinterpret_cast<uint4*>(smask)[256] = make_uint4(0, 0, 0, 0);
+    // 1. string-start mask of positions [ts-4, te) in LDS
+#pragma unroll
+    for (int u = 0; u < kU; ++u) reinterpret_cast<u32x4*>(smask + kMaskPad)[u * 64 + lane] = u32x4{0, 0, 0, 0};
+    if (lane0) *reinterpret_cast<u32x4*>(smask) = u32x4{0, 0, 0, 0};
     __syncthreads();
     int64_t cnt = 0, cnt_next = 0;
     for (;;) {
-      const int64_t idx = k0 + cnt + tid;
-      const int64_t v = idx <= a.n ? offsets[idx] : INT64_MAX;
       const bool in = v < te;
       if (in) {
         smask[v - ts + kMaskPad] = 0xFF;
-        if (cnt + tid < kOffCap) lds_off[cnt + tid] = v;
+        if (cnt + lane < kOffCap) soff[cnt + lane] = v;
       }
-      const int c = __syncthreads_count(in);
-      cnt_next += __syncthreads_count(v < te - 4);
+      const int c = __popcll(__ballot(in));
+      cnt_next += __popcll(__ballot(v < te - 4));
       cnt += c;
-      if (c < 256) break;
+      if (c < 64) break;
+      const int64_t idx = k0 + cnt + lane;
+      v = idx <= a.n ? offsets[idx] : INT64_MAX;
     }
-    const int64_t k1 = k0 + cnt;                           // boundaries in the window: [k0, k1)
+    const int64_t k1 = k0 + cnt;  // boundaries of this window: [k0, k1)
+    // 2. request tile t+1 (its window starts at boundary k0 + cnt_next)
+    u32x4 nx[kU];
+    const int64_t k0n = k0 + cnt_next;
+    if (t + 1 < t_end) {
+      batch_load(nx, data, te, lo, hi, lane);
+      v = k0n + lane <= a.n ? offsets[k0n + lane] : INT64_MAX;
+    }
     __syncthreads();
-
-    // 2. load the chunk and the dword before it (bytes outside [lo, hi) read as zero)
-    const int64_t c = ts + (int64_t)tid * 16;
-    uint4 x = make_uint4(0, 0, 0, 0);
-    uint32_t p = 0;
-    const bool inside = c >= a.lo && c + 16 <= a.hi;
-    if (inside) {
-      x = *reinterpret_cast<const uint4*>(a.data + c);
-      if (c - 4 >= a.lo) p = *reinterpret_cast<const uint32_t*>(a.data + c - 4);
-      else {
-        for (int b = 0; b < 4; ++b) { const int64_t q = c - 4 + b; if (q >= a.lo) p |= (uint32_t)a.data[q] << (8 * b); }
+    // 3. the dword before each chunk: lane l-1's last dword (lane 0: lane 63 of the previous slab)
+    uint32_t prev[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t rot = (uint32_t)__builtin_amdgcn_mov_dpp((int)x[u].w, kDppWaveRor1, 0xF, 0xF, true);
+      prev[u] = lane0 ? carry : rot;
+      carry = rot;
+    }
+    // 4. checks; a tile that is all ASCII with an ASCII halo cannot hold an error (6.4)
+    bool run = true;
+    if (ascii_skip == 0) {
+      uint32_t o = 0;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) o |= x[u].x | x[u].y | x[u].z | x[u].w | prev[u];
+      run = !__all((o & 0x80808080u) == 0);
+      if (run) ascii_skip = 3;
+    } else {
+      --ascii_skip;
+    }
+    uint32_t bad = 0;  // bit u: slab u saw a regular or end-check error
+    if (run) {
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const u32x4 s4 = reinterpret_cast<const u32x4*>(smask + kMaskPad)[u * 64 + lane];
+        const uint32_t sp = *reinterpret_cast<const uint32_t*>(smask + kMaskPad + u * 1024 + lane * 16 - 4);
+        uint32_t acc = 0, tail = 0;
+        MaskedCarry c = masked_halo(prev[u], sp);
+        masked_next(x[u].x, prev[u], s4.x, sp, c, acc, tail);
+        masked_next(x[u].y, x[u].x, s4.y, s4.x, c, acc, tail);
+        masked_next(x[u].z, x[u].y, s4.z, s4.y, c, acc, tail);
+        masked_next(x[u].w, x[u].z, s4.w, s4.z, c, acc, tail);
+        bad |= (acc | tail) ? (1u << u) : 0u;
       }
-    } else if (c - 4 < a.hi && c + 16 > a.lo) {
-      // edge chunk: its 20-byte window [c-4, c+16) overlaps [lo, hi); byte loads in range only
-      uint32_t w[5] = {0, 0, 0, 0, 0};
-      for (int k = 0; k < 20; ++k) {
-        const int64_t q = c - 4 + k;
-        if (q >= a.lo && q < a.hi) w[k >> 2] |= (uint32_t)a.data[q] << (8 * (k & 3));
-      }
-      p = w[0]; x = make_uint4(w[1], w[2], w[3], w[4]);
     }
-    const uint4 s4 = *reinterpret_cast<const uint4*>(smask + tid * 16 + kMaskPad);
-    const uint32_t sp = *reinterpret_cast<const uint32_t*>(smask + tid * 16 + kMaskPad - 4);
-
-    // 3. checks (section 6.4 skip when the chunk, its halo and the wave are all ASCII)
-    bool skip = false;
-    {
-      const uint32_t hi7 = (x.x | x.y | x.z | x.w | p) & 0x80808080u;
-      skip = __all(hi7 == 0);
-    }
-    uint32_t acc = 0;
-    uint32_t e[4], tl[4];
-    if (!skip) {
-      e[0] = masked_errors(x.x, p, s4.x, sp, &tl[0]);
-      e[1] = masked_errors(x.y, x.x, s4.y, s4.x, &tl[1]);
-      e[2] = masked_errors(x.z, x.y, s4.z, s4.y, &tl[2]);
-      e[3] = masked_errors(x.w, x.z, s4.w, s4.z, &tl[3]);
-      acc = e[0] | e[1] | e[2] | e[3] | tl[0] | tl[1] | tl[2] | tl[3];
-    }
-    // 4. rare: attribute errors to strings
-    if (__builtin_expect(acc != 0, 0)) {
-      int64_t last_k = -1;
-      for (int j = 0; j < 4; ++j) {
-        for (int b = 0; b < 4; ++b) {
-          const int64_t pos = c + 4 * j + b;
-          if ((tl[j] >> (8 * b)) & 0xFF) {
-            if (pos - 1 >= a.lo && pos <= a.hi) {
-              const int64_t k = string_of(pos - 1, offsets, k0, k1, lds_off);
-              if (k >= 0 && k < a.n && k != last_k) {
-                atomicMin(reinterpret_cast<unsigned long long*>(a.tmp + k),
-                          (unsigned long long)(pos - offsets[k]));
-              }
+    // 5. rare: give each error to its string (only the slabs that saw one)
+    if (__builtin_expect(bad != 0, 0)) {
+      int64_t cur_end = -1;  // end of the string of the last regular error noted by this lane
+      for (int u = 0; u < kU; ++u) {
+        if (!((bad >> u) & 1)) continue;
+        const u32x4 s4 = reinterpret_cast<const u32x4*>(smask + kMaskPad)[u * 64 + lane];
+        const uint32_t sp = *reinterpret_cast<const uint32_t*>(smask + kMaskPad + u * 1024 + lane * 16 - 4);
+        const uint32_t xs[5] = {prev[u], x[u].x, x[u].y, x[u].z, x[u].w};
+        const uint32_t ss[5] = {sp, s4.x, s4.y, s4.z, s4.w};
+        MaskedCarry c = masked_halo(prev[u], sp);
+        for (int j = 0; j < 4; ++j) {
+          uint32_t e = 0, tl = 0;
+          masked_next(xs[j + 1], xs[j], ss[j + 1], ss[j], c, e, tl);
+          uint32_t any = e | tl;
+          while (any) {
+            const int b = __builtin_ctz(any) >> 3;
+            any &= ~(0xFFu << (8 * b));
+            const int64_t pos = ts + u * 1024 + lane * 16 + 4 * j + b;
+            if (((tl >> (8 * b)) & 0xFF) && pos - 1 >= lo && pos <= hi) {
+              // end check of the string holding byte pos-1
+              const int64_t k = string_of(pos - 1, offsets, k0, k1, soff);
+              if (k >= 0 && k < a.n) note_error(a.tmp, k, pos - string_start(k, offsets, k0, k1, soff));
             }
-          }
-          if ((e[j] >> (8 * b)) & 0xFF) {
-            if (pos >= a.lo && pos < a.hi) {
-              const int64_t k = string_of(pos, offsets, k0, k1, lds_off);
-              if (k >= 0 && k < a.n && k != last_k) {
-                atomicMin(reinterpret_cast<unsigned long long*>(a.tmp + k),
-                          (unsigned long long)(pos - offsets[k]));
-                last_k = k;  // later positions of this string cannot be earlier
+            if (((e >> (8 * b)) & 0xFF) && pos >= lo && pos < hi && pos >= cur_end) {
+              // first regular error of a string (later ones in it cannot be earlier)
+              const int64_t k = string_of(pos, offsets, k0, k1, soff);
+              if (k >= 0 && k < a.n) {
+                note_error(a.tmp, k, pos - string_start(k, offsets, k0, k1, soff));
+                cur_end = string_end(k, offsets, k0, k1, soff);
               }
             }
           }
         }
       }
     }
-    // 5. next tile's window starts at te - 4
-    k0 += cnt_next;
+    k0 = k0n;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) x[u] = nx[u];
     __syncthreads();
   }
 }
@@ -256,11 +300,11 @@ hipError_t launch_batch(const uint8_t* data, const int64_t* offsets, int64_t n, 
   a.data = data; a.offsets = offsets; a.n = n; a.lo = a.hi = a.c0 = 0;
   a.flags = flags; a.first_err = first_err;
   a.tmp = first_err;  // per-string detections are staged in the output array
-  const int blocks = num_cus * (cfg.blocks_per_cu > 0 ? cfg.blocks_per_cu : 1);
+  const int waves = num_cus * (cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1);
   int fin_blocks = (int)((n + 255) / 256);
   if (fin_blocks > num_cus * 8) fin_blocks = num_cus * 8;
   hipLaunchKernelGGL(batch_init, dim3(fin_blocks), dim3(256), 0, st, a.tmp, n);
-  hipLaunchKernelGGL(batch_main, dim3(blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(batch_main, dim3(waves), dim3(64), 0, st, a);
   hipLaunchKernelGGL(batch_finalize, dim3(fin_blocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }

@@ -17,7 +17,7 @@ struct TuneSingle {
 };
 
 struct TuneBatch {
-  int blocks_per_cu = 4;      // persistent grid: 256-thread blocks per compute unit
+  int waves_per_cu = 16;      // persistent grid: one-wave workgroups per compute unit
   int ascii = 1;
 };
 

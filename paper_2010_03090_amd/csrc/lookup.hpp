@@ -61,25 +61,34 @@ __device__ __forceinline__ uint32_t align(uint32_t hi, uint32_t lo, uint32_t byt
 __device__ __forceinline__ uint32_t ge_mask7(uint32_t v, uint32_t k) {
   return __builtin_amdgcn_lerp(v, k, 0u);
 }
-// v_bitop3_b32 truth tables (operands a, b, c stand for 0xF0, 0xCC, 0xAA).
-// (m & a) | (~m & b)
-__device__ __forceinline__ uint32_t select_bits(uint32_t m, uint32_t a, uint32_t b) {
-  return __builtin_amdgcn_bitop3_b32(m, a, b, 0xCA);
+// v_bitop3_b32 computes any bitwise function of three operands; its 8-bit truth
+// table is the function applied to a = 0xF0, b = 0xCC, c = 0xAA.  Each helper
+// derives its table from its own formula at compile time.
+#define UTF8V_BITOP3(A, B, C, EXPR)                                                              \
+  __builtin_amdgcn_bitop3_b32((A), (B), (C),                                                    \
+                              ([](uint32_t a, uint32_t b, uint32_t c) constexpr { return (EXPR) & 0xFFu; })( \
+                                  0xF0u, 0xCCu, 0xAAu))
+
+__device__ __forceinline__ uint32_t select_bits(uint32_t m, uint32_t x, uint32_t y) {  // m ? x : y, bitwise
+  return UTF8V_BITOP3(m, x, y, (a & b) | (~a & c));
 }
-__device__ __forceinline__ uint32_t and3(uint32_t a, uint32_t b, uint32_t c) {
-  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x80);
+__device__ __forceinline__ uint32_t and3(uint32_t x, uint32_t y, uint32_t z) {
+  return UTF8V_BITOP3(x, y, z, a & b & c);
 }
-// (a | b) & c
-__device__ __forceinline__ uint32_t or_and(uint32_t a, uint32_t b, uint32_t c) {
-  return __builtin_amdgcn_bitop3_b32(a, b, c, 0xA8);
+__device__ __forceinline__ uint32_t or_and(uint32_t x, uint32_t y, uint32_t z) {  // (x | y) & z
+  return UTF8V_BITOP3(x, y, z, (a | b) & c);
 }
-// (a & b) | c
-__device__ __forceinline__ uint32_t and_or(uint32_t a, uint32_t b, uint32_t c) {
-  return __builtin_amdgcn_bitop3_b32(a, b, c, 0xEA);
+__device__ __forceinline__ uint32_t and_or(uint32_t x, uint32_t y, uint32_t z) {  // (x & y) | z
+  return UTF8V_BITOP3(x, y, z, (a & b) | c);
 }
-// acc | (a ^ b)
-__device__ __forceinline__ uint32_t or_xor(uint32_t acc, uint32_t a, uint32_t b) {
-  return __builtin_amdgcn_bitop3_b32(acc, a, b, 0xF6);
+__device__ __forceinline__ uint32_t or_xor(uint32_t acc, uint32_t x, uint32_t y) {  // acc | (x ^ y)
+  return UTF8V_BITOP3(acc, x, y, a | (b ^ c));
+}
+__device__ __forceinline__ uint32_t or_andn(uint32_t x, uint32_t y, uint32_t z) {  // x | (y & ~z)
+  return UTF8V_BITOP3(x, y, z, a | (b & ~c));
+}
+__device__ __forceinline__ uint32_t andn_and(uint32_t x, uint32_t y, uint32_t z) {  // x & ~y & z
+  return UTF8V_BITOP3(x, y, z, a & ~b & c);
 }
 
 // The three table lookups of section 6.1 from prepared indices:
@@ -176,6 +185,52 @@ __device__ __forceinline__ uint32_t chunk_errors(uint32_t acc, uint32_t x0, uint
   acc = errors_next(acc, x1, x0, c);
   acc = errors_next(acc, x2, x1, c);
   return errors_next(acc, x3, x2, c);
+}
+
+
+// ---- per-string masking (CSR batches) ----------------------------------------------------
+// s / sp: string-start masks (0xFF at positions where a string starts) of x and of the
+// dword before it.  Bytes of an earlier string count as zero (section 6: the stream
+// starts after zeros), so at a start prev1 is zero, must23 ignores bytes before the
+// start, and the string that ends at a start position gets the end check of 6.3.
+// gq at byte j: bit 7 = b[j] >= 0xE0, or b[j-1] >= 0xF0 when j is not a start.
+
+struct MaskedCarry {
+  uint32_t neg2, sh2, gq;
+};
+
+// Carried values of the dword p before a run (only its top bytes are used).
+__device__ __forceinline__ MaskedCarry masked_halo(uint32_t p, uint32_t sp) {
+  MaskedCarry c;
+  c.neg2 = perm(p, p, kSignSel);
+  c.sh2 = (p >> 4) & 0x07070707u;
+  // a | (b & ~c)
+  c.gq = or_andn(ge_mask7(p, 0x20202020u), ge_mask7(p << 8, 0x10101010u), sp);
+  return c;
+}
+
+// One dword x (string-start mask s) after xp (mask sp): regular errors ORed into acc,
+// end-check errors ORed into tail.
+__device__ __forceinline__ void masked_next(uint32_t x, uint32_t xp, uint32_t s, uint32_t sp, MaskedCarry& c,
+                                            uint32_t& acc, uint32_t& tail) {
+  const uint32_t prev1 = align(x, xp, 3);
+  const uint32_t s1 = align(s, sp, 3);                    // position i-1 starts a string
+  const uint32_t neg2 = perm(x, prev1, kSignSel);
+  const uint32_t sh2 = (x >> 4) & 0x07070707u;
+  const uint32_t gq = or_andn(ge_mask7(x, 0x20202020u), ge_mask7(prev1, 0x10101010u), s);
+  // prev1 of another string acts as zero: byte_1_high then reads 0x02 (neg1 cleared)
+  const uint32_t neg1 = align(neg2, c.neg2, 3) & ~s;
+  const uint32_t sc = lookup3(align(sh2, c.sh2, 3), prev1 & 0x07070707u, sh2, neg1, neg2, low_half_selector(prev1));
+  const uint32_t m = align(gq, c.gq, 2);                  // bit 7: must23 before the string masks
+  // must23 needs the bytes i-2 (i-3) in the string of i: no start at i, i-1 (i-2 is in gq)
+  const uint32_t m23 = andn_and(m, s | s1, 0x80808080u);
+  // end check of the string holding byte i-1, at a start position i
+  const uint32_t u = or_andn(ge_mask7(prev1, 0x40404040u), m, s1);
+  tail |= and3(u, s, 0x80808080u);
+  acc = or_xor(acc, sc, m23);
+  c.neg2 = neg2;
+  c.sh2 = sh2;
+  c.gq = gq;
 }
 
 // Index (0..3) of the lowest non-zero byte of a non-zero register.

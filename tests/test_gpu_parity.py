@@ -256,7 +256,7 @@ def test_tuning_invariance(u8):
             for ascii_ in (0, 1):
                 for waves in (1, 3, 16, 4096):
                     u8.set_config(unroll=unroll, ascii=ascii_, waves_per_cu=waves,
-                                  batch_blocks_per_cu=max(1, waves % 9), batch_ascii=ascii_)
+                                  batch_waves_per_cu=max(1, waves % 9), batch_ascii=ascii_)
                     for t, e in zip(tb, expected):
                         assert u8.first_error(t) == e, (unroll, ascii_, waves)
                     flags, ferr = u8.validate_batch(td, to)
