@@ -313,6 +313,7 @@ def bench_batch(u8, lib, synth, torch, dev, stream, sh, args):
         per_string = sub / (time.perf_counter() - t0)
         if not np.array_equal(outs.cpu().numpy(), expected[:sub]):
             raise SystemExit("wrong per-string result")
+    graph = bench_graph(u8, lib, torch, td, to, flags, ferr, nstr, offsets, expected, stream, sh, reps, warm)
     payload = int(offsets[-1] - offsets[0])
     algo = payload + 17 * nstr   # payload + offsets (8 B) + flag (1 B) + first_err (8 B) per string
     return {"workload": "1,000,000 strings, log-normal lengths (median 64 B, sigma 1.2, 1 B..64 KiB), "
@@ -322,7 +323,56 @@ def bench_batch(u8, lib, synth, torch, dev, stream, sh, args):
             "payload_GBps_warm": round(payload / warm / 1e9, 1),
             "algorithmic_GBps_warm": round(algo / warm / 1e9, 1),
             "per_string_launch_strings_per_s": round(per_string) if per_string else None,
-            "speedup_vs_per_string_launch": round(nstr / warm / per_string, 1) if per_string else None}
+            "speedup_vs_per_string_launch": round(nstr / warm / per_string, 1) if per_string else None,
+            "graph": graph}
+
+
+def bench_graph(u8, lib, torch, td, to, flags, ferr, nstr, offsets, expected, stream, sh, reps, warm):
+    """The same batch through the captured-graph entry point, and small batches direct vs graph."""
+    direct, graphed = lib.utf8v_validate_batch_async, lib.utf8v_validate_batch_graph
+
+    def call(fn, n):
+        rc = fn(td.data_ptr(), to.data_ptr(), n, flags.data_ptr(), ferr.data_ptr(), sh)
+        if rc:
+            raise u8.Utf8vError(rc, "batch")
+
+    ferr.fill_(-7)
+    call(graphed, nstr)
+    torch.cuda.synchronize()
+    got = ferr.cpu().numpy()
+    if not np.array_equal(got[expected >= 0], expected[expected >= 0]) or (got[expected < 0] != -1).any():
+        raise SystemExit("wrong graph batch result")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        call(graphed, nstr)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    g_warm = e0.elapsed_time(e1) * 1e-3 / reps
+    out = {"ms_warm_1m": round(g_warm * 1e3, 3), "ms_warm_1m_direct": round(warm * 1e3, 3)}
+    for n in (64, 4096):
+        row = {}
+        for name, fn in (("direct", direct), ("graph", graphed)):
+            for _ in range(50):
+                call(fn, n)
+            torch.cuda.synchronize()
+            k = 2000
+            t0 = time.perf_counter()
+            for _ in range(k):
+                call(fn, n)
+            torch.cuda.synchronize()
+            row[f"{name}_us_per_call_pipelined"] = round((time.perf_counter() - t0) / k * 1e6, 2)
+            lat = []
+            for _ in range(300):
+                t0 = time.perf_counter()
+                call(fn, n)
+                torch.cuda.synchronize()
+                lat.append(time.perf_counter() - t0)
+            row[f"{name}_us_latency_p50"] = round(float(np.median(lat)) * 1e6, 1)
+            if not np.array_equal(ferr[:n].cpu().numpy()[expected[:n] >= 0], expected[:n][expected[:n] >= 0]):
+                raise SystemExit(f"wrong {name} small-batch result")
+        out[f"n{n}"] = row
+    return out
 
 
 def cpu_baseline(host, n, seconds):

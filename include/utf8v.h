@@ -90,6 +90,20 @@ int utf8v_validate_batch_async(const uint8_t *data, const int64_t *offsets, int6
                                uint8_t *out_flags, int64_t *out_first_err, void *stream);
 
 /*
+ * utf8v_validate_batch_graph -- as utf8v_validate_batch_async, launched as one
+ * replay of a HIP graph (init, persistent validation, finalize) captured once per
+ * (device, stream) and launch configuration.  The kernels read their arguments
+ * from a per-stream device parameter block; each call enqueues a 64-byte copy of
+ * the new arguments (from one of 64 pinned staging slots) followed by the graph
+ * launch, so any batch shape replays the same graph.  The first call on a stream
+ * allocates the block and captures the graph (it must not run under stream
+ * capture); later calls allocate nothing.  A 65th call in flight on one stream
+ * waits for the first to have started.
+ */
+int utf8v_validate_batch_graph(const uint8_t *data, const int64_t *offsets, int64_t n,
+                               uint8_t *out_flags, int64_t *out_first_err, void *stream);
+
+/*
  * utf8v_check_offsets -- 1 if offsets[0..n] (device memory) is non-decreasing
  * with offsets[0] >= 0, else 0; negative status on error.  Synchronous.
  */

@@ -17,6 +17,7 @@ from . import _native
 from ._native import Config, Utf8vError, check, load
 
 __all__ = ["validate", "first_error", "validate_async", "validate_batch", "validate_batch_async",
+           "validate_batch_graph",
            "classify", "check_offsets", "get_config", "set_config", "num_cus", "read_ceiling", "copy",
            "Config", "Utf8vError", "load"]
 
@@ -77,6 +78,20 @@ def validate_batch_async(data, offsets, flags, first_err, stream=None) -> None:
     check(load().utf8v_validate_batch_async(data.data_ptr() if data.numel() else offsets.data_ptr(),
                                             offsets.data_ptr(), n, flags.data_ptr(), first_err.data_ptr(),
                                             _stream_handle(stream)), "utf8v_validate_batch_async")
+
+
+def validate_batch_graph(data, offsets, flags, first_err, stream=None) -> None:
+    """As validate_batch_async, launched as one replay of the per-stream captured HIP graph."""
+    torch = _torch()
+    _dev_u8(data, "data")
+    n = offsets.numel() - 1
+    if offsets.dtype != torch.int64 or not offsets.is_cuda or n < 0:
+        raise TypeError("offsets must be a CUDA int64 tensor with n+1 entries")
+    if n == 0:
+        return
+    check(load().utf8v_validate_batch_graph(data.data_ptr() if data.numel() else offsets.data_ptr(),
+                                            offsets.data_ptr(), n, flags.data_ptr(), first_err.data_ptr(),
+                                            _stream_handle(stream)), "utf8v_validate_batch_graph")
 
 
 def validate_batch(data, offsets, stream=None):

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <memory>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -19,14 +20,25 @@ thread_local int g_last_hip = 0;
 std::mutex g_mu;
 utf8v_config g_cfg = {4, 24, 1, 16, 1};
 
+constexpr int kParamSlots = 64;  // pinned parameter-block staging slots per stream (graph launches)
+
 struct Workspace {
   unsigned long long* dmin = nullptr;  // device: first detection position (kNone = none)
   int64_t* result = nullptr;           // device: first-error offset of the last call
   int* flag = nullptr;                 // device: scratch flag (offset checks)
   int64_t* host = nullptr;             // pinned host copy of result / flag
+  // graph-replayed batch launches
+  std::mutex mu;
+  utf8v::BatchArgs* dparams = nullptr;  // device parameter block read by the captured kernels
+  utf8v::BatchArgs* hslots = nullptr;   // pinned staging slots for the block's contents
+  hipEvent_t slot_done[kParamSlots] = {};
+  bool slot_used[kParamSlots] = {};
+  int next_slot = 0;
+  hipGraphExec_t exec = nullptr;
+  int graph_waves = 0, graph_cus = 0;
 };
 
-std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
 std::map<int, int> g_cus;
 
 int set_status(int s) { g_last_status = s; return s; }
@@ -63,26 +75,36 @@ int workspace(hipStream_t st, Workspace** out) {
   std::lock_guard<std::mutex> lk(g_mu);
   auto key = std::make_pair(dev, st);
   auto it = g_ws.find(key);
-  if (it != g_ws.end()) { *out = &it->second; return UTF8V_OK; }
-  Workspace w;
-  hipError_t e = hipMalloc(&w.dmin, 64);
-  if (e == hipSuccess) e = hipHostMalloc(&w.host, 64, hipHostMallocDefault);
+  if (it != g_ws.end()) { *out = it->second.get(); return UTF8V_OK; }
+  std::unique_ptr<Workspace> w(new Workspace);
+  hipError_t e = hipMalloc(&w->dmin, 64);
+  if (e == hipSuccess) e = hipHostMalloc(&w->host, 64, hipHostMallocDefault);
   if (e != hipSuccess) {
-    if (w.dmin) (void)hipFree(w.dmin);
+    if (w->dmin) (void)hipFree(w->dmin);
     return hip_fail(e);
   }
-  w.result = reinterpret_cast<int64_t*>(w.dmin) + 1;
-  w.flag = reinterpret_cast<int*>(w.dmin + 2);
+  w->result = reinterpret_cast<int64_t*>(w->dmin) + 1;
+  w->flag = reinterpret_cast<int*>(w->dmin + 2);
   const unsigned long long init[3] = {kNone, 0, 0};
-  e = hipMemcpy(w.dmin, init, sizeof init, hipMemcpyHostToDevice);
+  e = hipMemcpy(w->dmin, init, sizeof init, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    (void)hipFree(w.dmin);
-    (void)hipHostFree(w.host);
+    (void)hipFree(w->dmin);
+    (void)hipHostFree(w->host);
     return hip_fail(e);
   }
-  auto res = g_ws.emplace(key, w);
-  *out = &res.first->second;
+  *out = w.get();
+  g_ws.emplace(key, std::move(w));
   return UTF8V_OK;
+}
+
+void free_workspace(Workspace& w) {
+  if (w.exec) (void)hipGraphExecDestroy(w.exec);
+  for (int i = 0; i < kParamSlots; ++i)
+    if (w.slot_done[i]) (void)hipEventDestroy(w.slot_done[i]);
+  if (w.dparams) (void)hipFree(w.dparams);
+  if (w.hslots) (void)hipHostFree(w.hslots);
+  if (w.dmin) (void)hipFree(w.dmin);
+  if (w.host) (void)hipHostFree(w.host);
 }
 
 // 0 if the GPU can dereference p, else UTF8V_ENOTDEVICE.
@@ -190,6 +212,59 @@ int utf8_validate_batch(const uint8_t* data, const int64_t* offsets, int64_t n, 
   return set_status(UTF8V_OK);
 }
 
+int utf8v_validate_batch_graph(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* out_flags,
+                               int64_t* out_first_err, void* stream) {
+  if (n < 0) return set_status(UTF8V_EINVAL);
+  if (n == 0) return set_status(UTF8V_OK);
+  if (!data || !offsets || !out_flags || !out_first_err) return set_status(UTF8V_EINVAL);
+  for (const void* p : {(const void*)data, (const void*)offsets, (const void*)out_flags, (const void*)out_first_err}) {
+    int rc = check_device_ptr(p);
+    if (rc) return rc;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Workspace* ws = nullptr;
+  int rc = workspace(st, &ws);
+  if (rc) return rc;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const int cus = num_cus_of(dev) > 0 ? num_cus_of(dev) : 1;
+  const utf8v::TuneBatch cfg = tune_batch();
+  std::lock_guard<std::mutex> lk(ws->mu);
+  hipError_t e = hipSuccess;
+  if (!ws->dparams) {
+    e = hipMalloc(&ws->dparams, sizeof(utf8v::BatchArgs));
+    if (e == hipSuccess) e = hipHostMalloc(&ws->hslots, sizeof(utf8v::BatchArgs) * kParamSlots, hipHostMallocDefault);
+    for (int i = 0; e == hipSuccess && i < kParamSlots; ++i)
+      e = hipEventCreateWithFlags(&ws->slot_done[i], hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  if (!ws->exec || ws->graph_waves != cfg.waves_per_cu || ws->graph_cus != cus) {
+    if (ws->exec) {
+      e = hipStreamSynchronize(st);  // no replay of the old graph may still be running
+      if (e != hipSuccess) return hip_fail(e);
+      (void)hipGraphExecDestroy(ws->exec);
+      ws->exec = nullptr;
+    }
+    e = utf8v::capture_batch_graph(ws->dparams, cfg, cus, &ws->exec);
+    if (e != hipSuccess) return hip_fail(e);
+    ws->graph_waves = cfg.waves_per_cu;
+    ws->graph_cus = cus;
+  }
+  const int slot = ws->next_slot;
+  ws->next_slot = (slot + 1) % kParamSlots;
+  if (ws->slot_used[slot]) {
+    e = hipEventSynchronize(ws->slot_done[slot]);  // the copy out of this slot has run
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  ws->hslots[slot] = utf8v::batch_args(data, offsets, n, out_flags, out_first_err);
+  e = hipMemcpyAsync(ws->dparams, &ws->hslots[slot], sizeof(utf8v::BatchArgs), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipGraphLaunch(ws->exec, st);
+  if (e == hipSuccess) e = hipEventRecord(ws->slot_done[slot], st);
+  if (e != hipSuccess) return hip_fail(e);
+  ws->slot_used[slot] = true;
+  return set_status(UTF8V_OK);
+}
+
 int utf8v_check_offsets(const int64_t* offsets, int64_t n, void* stream) {
   if (n < 0 || offsets == nullptr) return set_status(UTF8V_EINVAL);
   int rc = check_device_ptr(offsets);
@@ -290,10 +365,7 @@ int utf8v_num_cus(void) {
 
 int utf8v_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
-  for (auto& kv : g_ws) {
-    (void)hipFree(kv.second.dmin);
-    (void)hipHostFree(kv.second.host);
-  }
+  for (auto& kv : g_ws) free_workspace(*kv.second);
   g_ws.clear();
   return set_status(UTF8V_OK);
 }

@@ -33,9 +33,14 @@ constexpr int kTile = kU * 1024;            // bytes per tile (one wave)
 constexpr int kMaskPad = 16;                // mask bytes kept before the tile (last 4 used)
 constexpr int kOffCap = 128;                // window boundaries cached in LDS for the error path
 
-__global__ void batch_init(int64_t* tmp, int64_t n) {
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
-    tmp[k] = kNoneRel;
+// Arguments come by value, or from a device parameter block when pa is not null
+// (graph replays: the captured launches keep pa, only the block's contents change).
+__device__ __forceinline__ BatchArgs args_of(const BatchArgs& a, const BatchArgs* pa) { return pa ? *pa : a; }
+
+__global__ void batch_init(BatchArgs a0, const BatchArgs* pa) {
+  const BatchArgs a = args_of(a0, pa);
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n; k += (int64_t)gridDim.x * blockDim.x)
+    a.tmp[k] = kNoneRel;
 }
 
 // First k in [0, n] with offsets[k] >= target (offsets[n] >= target is guaranteed by the caller).
@@ -127,7 +132,8 @@ __device__ __forceinline__ void batch_load(u32x4 (&x)[kU], const uint8_t* __rest
 // One wave per workgroup; each wave validates a contiguous run of 4 KiB tiles.  The
 // data and the first boundary offsets of tile t+1 are requested right after tile
 // t's boundary scan, before tile t is classified, so their latency overlaps it.
-__global__ __launch_bounds__(64) void batch_main(BatchArgs a) {
+__global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* pa) {
+  const BatchArgs a = args_of(a0, pa);
   __shared__ __align__(16) uint8_t smask[kTile + kMaskPad];  // string starts at positions [ts-16, te)
   __shared__ int64_t soff[kOffCap];                           // offsets[k0 ..] of the window
   const int lane = threadIdx.x;
@@ -259,7 +265,8 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a) {
 }
 
 // Per string: first detection -> first-error offset; flags.
-__global__ void batch_finalize(BatchArgs a) {
+__global__ void batch_finalize(BatchArgs a0, const BatchArgs* pa) {
+  const BatchArgs a = args_of(a0, pa);
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n; k += (int64_t)gridDim.x * blockDim.x) {
     const int64_t d = a.tmp[k];
     if (d == kNoneRel) {
@@ -293,20 +300,52 @@ hipError_t launch_offsets_check(const int64_t* offsets, int64_t n, int* bad, int
   return hipGetLastError();
 }
 
-hipError_t launch_batch(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* flags, int64_t* first_err,
-                        const TuneBatch& cfg, int num_cus, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
+static BatchArgs make_args(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* flags, int64_t* first_err) {
   BatchArgs a;
   a.data = data; a.offsets = offsets; a.n = n; a.lo = a.hi = a.c0 = 0;
   a.flags = flags; a.first_err = first_err;
   a.tmp = first_err;  // per-string detections are staged in the output array
+  return a;
+}
+
+// The three kernels with fixed grids (grid-stride init/finalize, persistent main), so
+// the same launches serve any batch; pa (device) overrides a when not null.
+static hipError_t launch_batch_kernels(const BatchArgs& a, const BatchArgs* pa, const TuneBatch& cfg, int num_cus,
+                                       hipStream_t st) {
   const int waves = num_cus * (cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1);
-  int fin_blocks = (int)((n + 255) / 256);
-  if (fin_blocks > num_cus * 8) fin_blocks = num_cus * 8;
-  hipLaunchKernelGGL(batch_init, dim3(fin_blocks), dim3(256), 0, st, a.tmp, n);
-  hipLaunchKernelGGL(batch_main, dim3(waves), dim3(64), 0, st, a);
-  hipLaunchKernelGGL(batch_finalize, dim3(fin_blocks), dim3(256), 0, st, a);
+  const int fin_blocks = num_cus * 8;
+  hipLaunchKernelGGL(batch_init, dim3(fin_blocks), dim3(256), 0, st, a, pa);
+  hipLaunchKernelGGL(batch_main, dim3(waves), dim3(64), 0, st, a, pa);
+  hipLaunchKernelGGL(batch_finalize, dim3(fin_blocks), dim3(256), 0, st, a, pa);
   return hipGetLastError();
+}
+
+hipError_t launch_batch(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* flags, int64_t* first_err,
+                        const TuneBatch& cfg, int num_cus, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  return launch_batch_kernels(make_args(data, offsets, n, flags, first_err), nullptr, cfg, num_cus, st);
+}
+
+hipError_t capture_batch_graph(const BatchArgs* dparams, const TuneBatch& cfg, int num_cus, hipGraphExec_t* exec) {
+  hipStream_t cap = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  hipGraph_t graph = nullptr;
+  e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const BatchArgs dummy = make_args(nullptr, nullptr, 0, nullptr, nullptr);
+    hipError_t le = launch_batch_kernels(dummy, dparams, cfg, num_cus, cap);
+    e = hipStreamEndCapture(cap, &graph);
+    if (e == hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cap);
+  return e;
+}
+
+BatchArgs batch_args(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* flags, int64_t* first_err) {
+  return make_args(data, offsets, n, flags, first_err);
 }
 
 }  // namespace utf8v

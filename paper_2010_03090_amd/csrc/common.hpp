@@ -64,6 +64,8 @@ hipError_t launch_single(const uint8_t* buf, uint64_t n, unsigned long long* dmi
                          const TuneSingle& cfg, int num_cus, hipStream_t st);
 hipError_t launch_batch(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* flags, int64_t* first_err,
                         const TuneBatch& cfg, int num_cus, hipStream_t st);
+hipError_t capture_batch_graph(const BatchArgs* dparams, const TuneBatch& cfg, int num_cus, hipGraphExec_t* exec);
+BatchArgs batch_args(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* flags, int64_t* first_err);
 hipError_t launch_offsets_check(const int64_t* offsets, int64_t n, int* bad, int num_cus, hipStream_t st);
 hipError_t launch_classify(const uint8_t* buf, uint64_t n, uint8_t* sc, uint8_t* err, hipStream_t st);
 hipError_t launch_read_ceiling(const uint8_t* buf, uint64_t n, uint32_t* out, int num_cus, hipStream_t st);

@@ -42,6 +42,9 @@ def test_host_only_error_paths():
     assert lib.utf8v_last_status() == _native.UTF8V_EINVAL
     assert lib.utf8v_validate_async(None, 0, None, None) == _native.UTF8V_EINVAL
     assert lib.utf8v_validate_batch_async(None, None, 0, None, None, None) == 0   # n == 0 is a no-op
+    assert lib.utf8v_validate_batch_graph(None, None, 0, None, None, None) == 0
+    assert lib.utf8v_validate_batch_graph(None, None, -2, None, None, None) == _native.UTF8V_EINVAL
+    assert lib.utf8v_validate_batch_graph(None, None, 5, None, None, None) == _native.UTF8V_EINVAL
     assert lib.utf8_validate(None, 3) is False
 
 

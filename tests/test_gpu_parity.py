@@ -239,6 +239,56 @@ def test_batch_config3_heavy_tail(u8):
     assert np.array_equal(e_o[expected >= 0], expected[expected >= 0])
 
 
+def test_batch_graph_replays(u8):
+    """The captured-graph entry point: every replay, with eager work between them, equals the oracle."""
+    cases = []
+    for seed, n in ((21, 50_000), (22, 7), (23, 3_000), (24, 1)):
+        data, offsets, _ = synth.lognormal_batch(n, seed)
+        f_o, e_o = oracle.first_error_batch(data, offsets)
+        cases.append((dev(data), dev(offsets), f_o, e_o))
+    side = synth.text(300_001, "mixed", 25)
+    synth.inject(side, 222_222, "overlong", 1)
+    side_exp = oracle.first_error(side)
+    tside = dev(side)
+    old = u8.get_config()
+    try:
+        for rep in range(3):
+            for i, (td, to, f_o, e_o) in enumerate(cases):
+                say(f"case: graph replay {rep} batch {i} n {e_o.size}")
+                n = e_o.size
+                flags = torch.full((n,), 9, dtype=torch.uint8, device="cuda")
+                ferr = torch.full((n,), -9, dtype=torch.int64, device="cuda")
+                u8.validate_batch_graph(td, to, flags, ferr)
+                # eager work on the same stream between replays
+                assert u8.first_error(tside) == side_exp
+                f2, e2 = u8.validate_batch(td, to)
+                torch.cuda.synchronize()
+                assert np.array_equal(ferr.cpu().numpy(), e_o), (rep, i)
+                assert np.array_equal(flags.cpu().numpy(), f_o), (rep, i)
+                assert np.array_equal(e2.cpu().numpy(), e_o)
+            # a changed launch configuration re-captures the graph
+            u8.set_config(batch_waves_per_cu=(3, 16, 5)[rep])
+        # many calls in flight on one stream (more than the staging slots), then one check each
+        td, to, f_o, e_o = cases[2]
+        outs = [torch.full((e_o.size,), -9, dtype=torch.int64, device="cuda") for _ in range(70)]
+        flags = torch.empty(e_o.size, dtype=torch.uint8, device="cuda")
+        for o in outs:
+            u8.validate_batch_graph(td, to, flags, o)
+        torch.cuda.synchronize()
+        for o in outs:
+            assert np.array_equal(o.cpu().numpy(), e_o)
+        # another stream gets its own graph
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            td, to, f_o, e_o = cases[0]
+            ferr = torch.empty(e_o.size, dtype=torch.int64, device="cuda")
+            u8.validate_batch_graph(td, to, flags.new_empty(e_o.size), ferr)
+        s.synchronize()
+        assert np.array_equal(ferr.cpu().numpy(), e_o)
+    finally:
+        u8.set_config(**old)
+
+
 def test_tuning_invariance(u8):
     """Every launch configuration gives identical results."""
     old = u8.get_config()
