@@ -21,8 +21,9 @@
  * accessible (hipMalloc memory, a torch CUDA tensor, managed or pinned host
  * memory) unless it is documented as a host pointer.  The caller owns all
  * buffers; the library never frees or retains them.  The library owns a small
- * per-(device, stream) workspace (created on first use, freed by
- * utf8v_release).
+ * per-(device, stream) workspace (about 8 bytes per wave of the batch grid, 128 KiB
+ * on 256 compute units; created and initialised on the stream by the first call
+ * that uses it, freed by utf8v_release).
  *
  * Errors.  Functions returning int return UTF8V_OK (0) or a negative status.
  * Invalid UTF-8 is a result, never an error.  No function aborts or throws.
@@ -91,9 +92,9 @@ int utf8v_validate_batch_async(const uint8_t *data, const int64_t *offsets, int6
 
 /*
  * utf8v_validate_batch_graph -- as utf8v_validate_batch_async, launched as one
- * replay of a HIP graph (init, persistent validation, finalize) captured once per
- * (device, stream) and launch configuration.  The kernels read their arguments
- * from a per-stream device parameter block; each call enqueues a 64-byte copy of
+ * replay of a HIP graph (the persistent validation kernel) captured once per
+ * (device, stream) and launch configuration.  The kernel reads its arguments
+ * from a per-stream device parameter block; each call enqueues a 48-byte copy of
  * the new arguments (from one of 64 pinned staging slots) followed by the graph
  * launch, so any batch shape replays the same graph.  The first call on a stream
  * allocates the block and captures the graph (it must not run under stream

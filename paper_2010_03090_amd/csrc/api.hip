@@ -20,13 +20,15 @@ thread_local int g_last_hip = 0;
 std::mutex g_mu;
 utf8v_config g_cfg = {4, 24, 1, 16, 1};
 
-constexpr int kParamSlots = 64;  // pinned parameter-block staging slots per stream (graph launches)
+constexpr int kParamSlots = 64;
+constexpr int kBatchSlotsPerCu = 64;  // = the largest batch_waves_per_cu  // pinned parameter-block staging slots per stream (graph launches)
 
 struct Workspace {
   unsigned long long* dmin = nullptr;  // device: first detection position (kNone = none)
   int64_t* result = nullptr;           // device: first-error offset of the last call
   int* flag = nullptr;                 // device: scratch flag (offset checks)
   int64_t* host = nullptr;             // pinned host copy of result / flag
+  unsigned long long* slot = nullptr;  // device: batch cross-wave slots (self-cleaning), kBatchSlotsPerCu per CU
   // graph-replayed batch launches
   std::mutex mu;
   utf8v::BatchArgs* dparams = nullptr;  // device parameter block read by the captured kernels
@@ -67,29 +69,42 @@ int num_cus_of(int dev) {
   return v;
 }
 
-// Workspace of (current device, stream); created on first use with dmin = none.
+void free_workspace(Workspace& w) {
+  if (w.exec) (void)hipGraphExecDestroy(w.exec);
+  for (int i = 0; i < kParamSlots; ++i)
+    if (w.slot_done[i]) (void)hipEventDestroy(w.slot_done[i]);
+  if (w.dparams) (void)hipFree(w.dparams);
+  if (w.hslots) (void)hipHostFree(w.hslots);
+  if (w.slot) (void)hipFree(w.slot);
+  if (w.dmin) (void)hipFree(w.dmin);
+  if (w.host) (void)hipHostFree(w.host);
+}
+
+// Workspace of (current device, stream); created on first use with dmin = none and
+// empty batch slots (the initialisation is enqueued on the stream).
 int workspace(hipStream_t st, Workspace** out) {
   int dev = 0;
   int rc = current_device(&dev);
   if (rc) return rc;
+  const int cus = num_cus_of(dev) > 0 ? num_cus_of(dev) : 1;
   std::lock_guard<std::mutex> lk(g_mu);
   auto key = std::make_pair(dev, st);
   auto it = g_ws.find(key);
   if (it != g_ws.end()) { *out = it->second.get(); return UTF8V_OK; }
   std::unique_ptr<Workspace> w(new Workspace);
+  const int slots = cus * kBatchSlotsPerCu;
   hipError_t e = hipMalloc(&w->dmin, 64);
   if (e == hipSuccess) e = hipHostMalloc(&w->host, 64, hipHostMallocDefault);
-  if (e != hipSuccess) {
-    if (w->dmin) (void)hipFree(w->dmin);
-    return hip_fail(e);
+  if (e == hipSuccess) e = hipMalloc(&w->slot, sizeof(unsigned long long) * slots);
+  if (e == hipSuccess) {
+    w->result = reinterpret_cast<int64_t*>(w->dmin) + 1;
+    w->flag = reinterpret_cast<int*>(w->dmin + 2);
+    const unsigned long long init[3] = {kNone, 0, 0};
+    e = hipMemcpy(w->dmin, init, sizeof init, hipMemcpyHostToDevice);
   }
-  w->result = reinterpret_cast<int64_t*>(w->dmin) + 1;
-  w->flag = reinterpret_cast<int*>(w->dmin + 2);
-  const unsigned long long init[3] = {kNone, 0, 0};
-  e = hipMemcpy(w->dmin, init, sizeof init, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = utf8v::launch_batch_slots_init(w->slot, slots, st);
   if (e != hipSuccess) {
-    (void)hipFree(w->dmin);
-    (void)hipHostFree(w->host);
+    free_workspace(*w);
     return hip_fail(e);
   }
   *out = w.get();
@@ -97,15 +112,6 @@ int workspace(hipStream_t st, Workspace** out) {
   return UTF8V_OK;
 }
 
-void free_workspace(Workspace& w) {
-  if (w.exec) (void)hipGraphExecDestroy(w.exec);
-  for (int i = 0; i < kParamSlots; ++i)
-    if (w.slot_done[i]) (void)hipEventDestroy(w.slot_done[i]);
-  if (w.dparams) (void)hipFree(w.dparams);
-  if (w.hslots) (void)hipHostFree(w.hslots);
-  if (w.dmin) (void)hipFree(w.dmin);
-  if (w.host) (void)hipHostFree(w.host);
-}
 
 // 0 if the GPU can dereference p, else UTF8V_ENOTDEVICE.
 int check_device_ptr(const void* p) {
@@ -193,12 +199,15 @@ int utf8v_validate_batch_async(const uint8_t* data, const int64_t* offsets, int6
     int rc = check_device_ptr(p);
     if (rc) return rc;
   }
-  int dev = 0;
-  int rc = current_device(&dev);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Workspace* ws = nullptr;
+  int rc = workspace(st, &ws);
   if (rc) return rc;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
   const int cus = num_cus_of(dev);
-  hipError_t e = utf8v::launch_batch(data, offsets, n, out_flags, out_first_err, tune_batch(), cus > 0 ? cus : 1,
-                                     reinterpret_cast<hipStream_t>(stream));
+  const utf8v::BatchArgs a = utf8v::batch_args(data, offsets, n, out_flags, out_first_err, ws->slot);
+  hipError_t e = utf8v::launch_batch(a, tune_batch(), cus > 0 ? cus : 1, st);
   if (e != hipSuccess) return hip_fail(e);
   return set_status(UTF8V_OK);
 }
@@ -256,7 +265,7 @@ int utf8v_validate_batch_graph(const uint8_t* data, const int64_t* offsets, int6
     e = hipEventSynchronize(ws->slot_done[slot]);  // the copy out of this slot has run
     if (e != hipSuccess) return hip_fail(e);
   }
-  ws->hslots[slot] = utf8v::batch_args(data, offsets, n, out_flags, out_first_err);
+  ws->hslots[slot] = utf8v::batch_args(data, offsets, n, out_flags, out_first_err, ws->slot);
   e = hipMemcpyAsync(ws->dparams, &ws->hslots[slot], sizeof(utf8v::BatchArgs), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipGraphLaunch(ws->exec, st);
   if (e == hipSuccess) e = hipEventRecord(ws->slot_done[slot], st);

@@ -6,21 +6,27 @@
 // section 6.3.  Results: flags[k] = 1 if valid, first_err[k] = start of the
 // first ill-formed character relative to the string start, or -1.
 //
-// Work is split by bytes, not by strings: the byte range [offsets[0],
-// offsets[n]] is cut into 4 KiB tiles (one 16-byte chunk per lane of a
-// 256-thread block) and a persistent grid gives each block a contiguous run of
-// tiles, so a 64 MiB string and a million 64-byte strings load-balance alike.
+// One launch does everything.  Work is split by bytes, not by strings: the
+// byte range [offsets[0], offsets[n]] is cut into 4 KiB tiles and a persistent
+// grid of one-wave workgroups gives each wave a contiguous run of tiles, so a
+// 64 MiB string and a million 64-byte strings load-balance alike.
 //
-// Per tile the block writes a byte mask of string starts into LDS (from the
-// offsets falling in the tile), and each lane validates its chunk with the
-// bytes of other strings masked to zero:
+// Per tile the wave writes a byte mask of string starts into LDS (from the
+// offsets falling in the tile), and each lane validates its 16-byte chunks
+// with the bytes of other strings masked to zero:
 //   - the lookup checks of section 6.1-6.2 at position i use prev1/prev2/prev3
 //     only when they belong to the string of position i;
 //   - at every string boundary i, the string that ends there (the one holding
 //     byte i-1) gets the end check of section 6.3 on its own last bytes.
-// A lane that sees any error finds the strings concerned and lowers their
-// first detection position with atomicMin; a per-string pass turns it into the
-// first-error offset.
+// Lanes that see an error record, per position, a bit in one of two LDS
+// bitmaps (regular error / end-check error).  Then the wave writes the result
+// of every string whose end lies in the tile: its first detection is the first
+// bit in its own range.  A string that runs across tiles carries its first
+// detection in a wave-uniform register; one that runs across waves gets a
+// partial minimum from every wave it touches, in a workspace slot of the wave
+// holding its start, and the last of those waves to arrive (an arrival count
+// kept in the same 64-bit word) writes its result and resets the slot, so the
+// workspace is clean again when the kernel ends.
 #include "common.hpp"
 #include "lookup.hpp"
 
@@ -37,12 +43,6 @@ constexpr int kOffCap = 128;                // window boundaries cached in LDS f
 // (graph replays: the captured launches keep pa, only the block's contents change).
 __device__ __forceinline__ BatchArgs args_of(const BatchArgs& a, const BatchArgs* pa) { return pa ? *pa : a; }
 
-__global__ void batch_init(BatchArgs a0, const BatchArgs* pa) {
-  const BatchArgs a = args_of(a0, pa);
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n; k += (int64_t)gridDim.x * blockDim.x)
-    a.tmp[k] = kNoneRel;
-}
-
 // First k in [0, n] with offsets[k] >= target (offsets[n] >= target is guaranteed by the caller).
 __device__ int64_t wave_lower_bound(const int64_t* __restrict__ offsets, int64_t n, int64_t target, int lane) {
   int64_t lo = 0, hi = n;  // answer in [lo, hi]
@@ -57,20 +57,6 @@ __device__ int64_t wave_lower_bound(const int64_t* __restrict__ offsets, int64_t
     hi = new_hi < hi ? new_hi : hi;
   }
   return lo;
-}
-
-// String holding position pos: the last k in [k0-1, k1-1] with offsets[k] <= pos.
-// Boundaries k0..k1-1 are cached in LDS (soff) when there are at most kOffCap of them.
-__device__ int64_t string_of(int64_t pos, const int64_t* __restrict__ offsets, int64_t k0, int64_t k1,
-                             const int64_t* soff) {
-  const bool cached = k1 - k0 <= kOffCap;
-  int64_t lo = k0, hi = k1;  // first k in [k0, k1] with offsets[k] > pos
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    const int64_t v = cached ? soff[mid - k0] : offsets[mid];
-    if (v <= pos) lo = mid + 1; else hi = mid;
-  }
-  return lo - 1;
 }
 
 // Bytes [q, q+4) of the batch range [lo, hi) as a dword, zero outside the range.
@@ -99,20 +85,10 @@ __device__ u32x4 edge_chunk(const uint8_t* __restrict__ data, int64_t c, int64_t
   return u32x4{w[0], w[1], w[2], w[3]};
 }
 
-__device__ __forceinline__ void note_error(int64_t* tmp, int64_t k, int64_t rel) {
-  atomicMin(reinterpret_cast<unsigned long long*>(tmp + k), (unsigned long long)rel);
-}
-
-// Start offset of string k, for k in [k0-1, k1-1] (LDS when cached).
-__device__ __forceinline__ int64_t string_start(int64_t k, const int64_t* __restrict__ offsets, int64_t k0, int64_t k1,
-                                                const int64_t* soff) {
-  return (k >= k0 && k1 - k0 <= kOffCap) ? soff[k - k0] : offsets[k];
-}
-
-// End offset of string k (the next boundary), for k in [k0-1, k1-1].
-__device__ __forceinline__ int64_t string_end(int64_t k, const int64_t* __restrict__ offsets, int64_t k0, int64_t k1,
-                                              const int64_t* soff) {
-  return (k + 1 < k1 && k1 - k0 <= kOffCap) ? soff[k + 1 - k0] : offsets[k + 1];
+// Start offset of string k, for k in [k0, n] (LDS when cached).
+__device__ __forceinline__ int64_t boundary(int64_t k, const int64_t* __restrict__ offsets, int64_t k0, int64_t k1,
+                                            const int64_t* soff) {
+  return (k >= k0 && k < k0 + kOffCap && k < k1) ? soff[k - k0] : offsets[k];
 }
 
 // Loads of one tile: interior tiles read whole chunks (non-temporal); tiles at the
@@ -129,18 +105,134 @@ __device__ __forceinline__ void batch_load(u32x4 (&x)[kU], const uint8_t* __rest
   }
 }
 
-// One wave per workgroup; each wave validates a contiguous run of 4 KiB tiles.  The
-// data and the first boundary offsets of tile t+1 are requested right after tile
-// t's boundary scan, before tile t is classified, so their latency overlaps it.
+constexpr int kMaskWords = kTile / 32;       // words of one per-position error bitmap
+
+__device__ __forceinline__ bool bit_at(const uint32_t* m, int r) { return (m[r >> 5] >> (r & 31)) & 1u; }
+
+// Which words of a bitmap hold a set bit: bit w of (nz.lo | nz.hi << 64).  Wave-uniform.
+struct WordSummary {
+  uint64_t lo, hi;
+};
+
+__device__ __forceinline__ WordSummary summarize(const uint32_t* m, int lane) {
+  return WordSummary{__ballot(m[lane] != 0u), __ballot(m[lane + 64] != 0u)};
+}
+
+// First word index >= w whose summary bit is set, or kMaskWords.
+__device__ __forceinline__ int next_word(const WordSummary& nz, int w) {
+  if (w < 64) {
+    const uint64_t l = nz.lo & (~0ull << w);
+    if (l) return __builtin_ctzll(l);
+    w = 64;
+  }
+  if (w >= kMaskWords) return kMaskWords;
+  const uint64_t h = nz.hi & (~0ull << (w - 64));
+  return h ? 64 + __builtin_ctzll(h) : kMaskWords;
+}
+
+// First set bit of m among tile positions [a, b) (0 <= a <= b <= kTile), or -1.  Only
+// words flagged in the summary are read: a word strictly inside the range that holds a
+// bit ends the search, so at most the two edge words are read in vain.
+__device__ int first_bit(const uint32_t* m, const WordSummary& nz, int a, int b) {
+  if (a >= b) return -1;
+  const int wb = (b - 1) >> 5;
+  for (int w = next_word(nz, a >> 5); w <= wb; w = next_word(nz, w + 1)) {
+    const int base = w * 32;
+    uint32_t v = m[w];
+    if (a > base) v &= ~0u << (a - base);
+    if (b < base + 32) v &= (1u << (b - base)) - 1u;
+    if (v) return base + __builtin_ctz(v);
+  }
+  return -1;
+}
+
+// One bit per byte of an error dword: bit b set iff byte b is non-zero.
+__device__ __forceinline__ uint32_t nonzero_bytes(uint32_t e) {
+  const uint32_t t = (((e & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | e) & 0x80808080u;
+  return ((t >> 7) * 0x00204081u) >> 21 & 0xFu;
+}
+
+// First detection d (relative) -> first-error offset s (section 6.3 applied backwards:
+// the latest k in [d-3, d] that does not cut a character), for a string of length
+// len whose bytes are b[0..len).  The six bytes before d are read at once.
+__device__ __forceinline__ int64_t resolve_first_error(const uint8_t* b, int64_t len, int64_t d) {
+  uint32_t w[7];  // w[i] = byte d-i (0 outside the string)
+#pragma unroll
+  for (int i = 1; i <= 6; ++i) {
+    const int64_t q = d - i;
+    w[i] = (q >= 0 && q < len) ? b[q] : 0u;
+  }
+#pragma unroll
+  for (int i = 0; i <= 3; ++i)  // k = d - i
+    if (d - i >= 0 && w[i + 1] < 0xC0 && w[i + 2] < 0xE0 && w[i + 3] < 0xF0) return d - i;
+  return d;
+}
+
+__device__ __forceinline__ void write_result(const BatchArgs& a, int64_t k, const uint8_t* b, int64_t len, int64_t d) {
+  if (d == kNoneRel) {
+    a.flags[k] = 1;
+    a.first_err[k] = -1;
+  } else {
+    a.flags[k] = 0;
+    a.first_err[k] = resolve_first_error(b, len, d);
+  }
+}
+
+// Wave-uniform 64-bit value kept in scalar registers.
+__device__ __forceinline__ int64_t uniform(int64_t v) {
+  const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi32 = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi32 << 32) | lo32);
+}
+
+// Wave holding position p (tiles are dealt out in runs of `per`).
+__device__ __forceinline__ int64_t wave_of(int64_t p, int64_t c0, int64_t per) { return (p - c0) / kTile / per; }
+
+// Cross-wave slot word: arrivals in bits 40..63, the least partial first detection in
+// bits 0..39 (kSlotNone = none; a string is shorter than 2^40 bytes).  One 64-bit word,
+// so arrival and minimum are published together without a memory fence.
+constexpr int kSlotShift = 40;
+constexpr uint64_t kSlotNone = (1ull << kSlotShift) - 1;
+
+// String k runs across waves ws < we; this wave contributes the first detection d it
+// saw in its part (kNoneRel if none).  The last contributor writes the result and
+// empties the slot.  Lane 0.
+__device__ void cross_wave(const BatchArgs& a, int64_t k, int64_t st, int64_t en, int64_t d, int64_t c0,
+                           int64_t per) {
+  const int64_t ws = wave_of(st, c0, per), we = wave_of(en, c0, per);
+  unsigned long long* slot = a.slot + ws;
+  const uint64_t mine = d == kNoneRel ? kSlotNone : (uint64_t)d;
+  uint64_t old = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint64_t arrived, best;
+  for (;;) {  // lock-free: a failed exchange means another wave's succeeded
+    arrived = (old >> kSlotShift) + 1;
+    const uint64_t prev = old & kSlotNone;
+    best = prev < mine ? prev : mine;
+    const uint64_t seen = atomicCAS(slot, (unsigned long long)old, (unsigned long long)((arrived << kSlotShift) | best));
+    if (seen == old) break;
+    old = seen;
+  }
+  if ((int64_t)arrived == we - ws + 1) {
+    atomicExch(slot, (unsigned long long)kSlotNone);
+    write_result(a, k, a.data + st, en - st, best == kSlotNone ? kNoneRel : (int64_t)best);
+  }
+}
+
+// One wave per workgroup; each wave validates a contiguous run of tiles.  The data
+// and the first boundary offsets of tile t+1 are requested right after tile t's
+// boundary scan, before tile t is classified, so their latency overlaps it.
 __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* pa) {
   const BatchArgs a = args_of(a0, pa);
   __shared__ __align__(16) uint8_t smask[kTile + kMaskPad];  // string starts at positions [ts-16, te)
   __shared__ int64_t soff[kOffCap];                           // offsets[k0 ..] of the window
+  __shared__ uint32_t regm[kMaskWords];                       // regular error at tile position r
+  __shared__ uint32_t endm[kMaskWords];                       // end-check error at tile position r
   const int lane = threadIdx.x;
   const int64_t* __restrict__ offsets = a.offsets;
   const uint8_t* __restrict__ data = a.data;
   // the byte range is read on the device, so one launch shape serves any batch
-  const int64_t lo = offsets[0], hi = offsets[a.n];
+  const int64_t n = a.n;
+  const int64_t lo = uniform(offsets[0]), hi = uniform(offsets[n]);
   const int64_t c0 = lo - (int64_t)((reinterpret_cast<uintptr_t>(data) + (uintptr_t)lo) & 15);
   // tiles cover [c0, hi]: position hi holds the end check of the last string
   const int64_t tiles = (hi + 1 - c0 + kTile - 1) / kTile;
@@ -148,24 +240,29 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
   int64_t t = (int64_t)blockIdx.x * per;
   const int64_t t_end = t + per < tiles ? t + per : tiles;
   if (t >= t_end) return;
-  int64_t k0 = wave_lower_bound(offsets, a.n, c0 + t * kTile - 4, lane);
-  uint32_t carry = range_dword(data, c0 + t * kTile - 4, lo, hi);  // the dword before the first tile
+  const int64_t wave_lo = c0 + t * kTile;
+  regm[lane] = regm[lane + 64] = 0u;
+  endm[lane] = endm[lane + 64] = 0u;
+  int64_t k0 = uniform(wave_lower_bound(offsets, n, wave_lo - 4, lane));
+  uint32_t carry = range_dword(data, wave_lo - 4, lo, hi);  // the dword before the first tile
   const bool lane0 = lane == 0;
   int ascii_skip = 0;
+  // the string open at the wave start (it began in an earlier wave) is found in the first window
+  int64_t open_k = -2, open_st = 0, open_d = kNoneRel;
 
   u32x4 x[kU];
-  batch_load(x, data, c0 + t * kTile, lo, hi, lane);
-  int64_t v = k0 + lane <= a.n ? offsets[k0 + lane] : INT64_MAX;
+  batch_load(x, data, wave_lo, lo, hi, lane);
+  int64_t v = k0 + lane <= n ? offsets[k0 + lane] : INT64_MAX;
 
   for (; t < t_end; ++t) {
     const int64_t ts = c0 + t * kTile;
     const int64_t te = ts + kTile;
-    // 1. string-start mask of positions [ts-4, te) in LDS
+    // 1. string-start mask of positions [ts-4, te) in LDS; boundaries [k0, k1) of the window
 #pragma unroll
     for (int u = 0; u < kU; ++u) reinterpret_cast<u32x4*>(smask + kMaskPad)[u * 64 + lane] = u32x4{0, 0, 0, 0};
     if (lane0) *reinterpret_cast<u32x4*>(smask) = u32x4{0, 0, 0, 0};
     __syncthreads();
-    int64_t cnt = 0, cnt_next = 0;
+    int64_t cnt = 0, cnt_next = 0, cnt_before = 0;
     for (;;) {
       const bool in = v < te;
       if (in) {
@@ -174,20 +271,26 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
       }
       const int c = __popcll(__ballot(in));
       cnt_next += __popcll(__ballot(v < te - 4));
+      cnt_before += __popcll(__ballot(v < ts));
       cnt += c;
       if (c < 64) break;
       const int64_t idx = k0 + cnt + lane;
-      v = idx <= a.n ? offsets[idx] : INT64_MAX;
+      v = idx <= n ? offsets[idx] : INT64_MAX;
     }
-    const int64_t k1 = k0 + cnt;  // boundaries of this window: [k0, k1)
+    const int64_t k1 = uniform(k0 + cnt);          // boundaries in [ts-4, te): [k0, k1)
+    const int64_t kb = uniform(k0 + cnt_before);   // boundaries in [ts, te): [kb, k1)
     // 2. request tile t+1 (its window starts at boundary k0 + cnt_next)
     u32x4 nx[kU];
     const int64_t k0n = k0 + cnt_next;
     if (t + 1 < t_end) {
       batch_load(nx, data, te, lo, hi, lane);
-      v = k0n + lane <= a.n ? offsets[k0n + lane] : INT64_MAX;
+      v = k0n + lane <= n ? offsets[k0n + lane] : INT64_MAX;
     }
     __syncthreads();
+    if (open_k == -2) {  // first tile of the wave
+      open_k = kb - 1;
+      if (open_k >= 0) open_st = uniform(boundary(open_k, offsets, k0, k1, soff));
+    }
     // 3. the dword before each chunk: lane l-1's last dword (lane 0: lane 63 of the previous slab)
     uint32_t prev[kU];
 #pragma unroll
@@ -222,9 +325,9 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
         bad |= (acc | tail) ? (1u << u) : 0u;
       }
     }
-    // 5. rare: give each error to its string (only the slabs that saw one)
+    const bool tile_bad = __any(bad != 0);
+    // 5. rare: per-position error bits of the slabs that saw an error
     if (__builtin_expect(bad != 0, 0)) {
-      int64_t cur_end = -1;  // end of the string of the last regular error noted by this lane
       for (int u = 0; u < kU; ++u) {
         if (!((bad >> u) & 1)) continue;
         const u32x4 s4 = reinterpret_cast<const u32x4*>(smask + kMaskPad)[u * 64 + lane];
@@ -232,28 +335,81 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
         const uint32_t xs[5] = {prev[u], x[u].x, x[u].y, x[u].z, x[u].w};
         const uint32_t ss[5] = {sp, s4.x, s4.y, s4.z, s4.w};
         MaskedCarry c = masked_halo(prev[u], sp);
+        uint32_t rbits = 0, ebits = 0;
         for (int j = 0; j < 4; ++j) {
           uint32_t e = 0, tl = 0;
           masked_next(xs[j + 1], xs[j], ss[j + 1], ss[j], c, e, tl);
-          uint32_t any = e | tl;
-          while (any) {
-            const int b = __builtin_ctz(any) >> 3;
-            any &= ~(0xFFu << (8 * b));
-            const int64_t pos = ts + u * 1024 + lane * 16 + 4 * j + b;
-            if (((tl >> (8 * b)) & 0xFF) && pos - 1 >= lo && pos <= hi) {
-              // end check of the string holding byte pos-1
-              const int64_t k = string_of(pos - 1, offsets, k0, k1, soff);
-              if (k >= 0 && k < a.n) note_error(a.tmp, k, pos - string_start(k, offsets, k0, k1, soff));
-            }
-            if (((e >> (8 * b)) & 0xFF) && pos >= lo && pos < hi && pos >= cur_end) {
-              // first regular error of a string (later ones in it cannot be earlier)
-              const int64_t k = string_of(pos, offsets, k0, k1, soff);
-              if (k >= 0 && k < a.n) {
-                note_error(a.tmp, k, pos - string_start(k, offsets, k0, k1, soff));
-                cur_end = string_end(k, offsets, k0, k1, soff);
-              }
-            }
+          rbits |= nonzero_bytes(e) << (4 * j);
+          ebits |= nonzero_bytes(tl) << (4 * j);
+        }
+        const int64_t base = ts + u * 1024 + lane * 16;
+        if (base - 1 < lo || base + 16 > hi) {  // chunk at an edge of the batch range
+          for (int b = 0; b < 16; ++b) {
+            const int64_t pos = base + b;
+            if (!(pos >= lo && pos < hi)) rbits &= ~(1u << b);
+            if (!(pos - 1 >= lo && pos <= hi)) ebits &= ~(1u << b);
           }
+        }
+        reinterpret_cast<uint16_t*>(regm)[u * 64 + lane] = (uint16_t)rbits;
+        reinterpret_cast<uint16_t*>(endm)[u * 64 + lane] = (uint16_t)ebits;
+      }
+    }
+    __syncthreads();
+    // the tile's bytes, for resolving first errors of the strings inside it (the mask is spent)
+    const uint8_t* tile_bytes = smask + kMaskPad;
+    if (tile_bad) {
+#pragma unroll
+      for (int u = 0; u < kU; ++u) reinterpret_cast<u32x4*>(smask + kMaskPad)[u * 64 + lane] = x[u];
+      __syncthreads();
+    }
+    // 6. results of the strings that end in this tile (end positions in [ts, te))
+    WordSummary nz{0, 0};
+    if (tile_bad) nz = summarize(regm, lane);
+    if (open_k >= 0) {  // the string open at ts
+      const bool ends = kb < k1;
+      const int64_t en = ends ? uniform(boundary(kb, offsets, k0, k1, soff)) : te;
+      if (tile_bad) {
+        const int r = first_bit(regm, nz, 0, (int)(en - ts));
+        if (r >= 0 && ts + r - open_st < open_d) open_d = ts + r - open_st;
+        if (ends && bit_at(endm, (int)(en - ts)) && en - open_st < open_d) open_d = en - open_st;
+      }
+      if (ends) {
+        if (lane0) {
+          if (open_st >= wave_lo) write_result(a, open_k, data + open_st, en - open_st, open_d);
+          else cross_wave(a, open_k, open_st, en, open_d, c0, per);
+        }
+        open_k = -1;
+      }
+    }
+    for (int64_t j0 = kb; j0 < k1 - 1; j0 += 64) {  // strings that start and end in the tile
+      const int64_t k = j0 + lane;
+      if (k < k1 - 1) {
+        const int64_t st = boundary(k, offsets, k0, k1, soff), en = boundary(k + 1, offsets, k0, k1, soff);
+        int64_t d = kNoneRel;
+        if (tile_bad && en > st) {
+          const int r = first_bit(regm, nz, (int)(st - ts), (int)(en - ts));
+          if (r >= 0) d = ts + r - st;
+          if (bit_at(endm, (int)(en - ts)) && en - st < d) d = en - st;
+        }
+        write_result(a, k, tile_bytes + (st - ts), en - st, d);
+      }
+    }
+    if (k1 - 1 >= kb && k1 <= n) {  // the string starting here that runs past te
+      open_k = k1 - 1;
+      open_st = uniform(boundary(open_k, offsets, k0, k1, soff));
+      open_d = kNoneRel;
+      if (tile_bad) {
+        const int r = first_bit(regm, nz, (int)(open_st - ts), kTile);
+        if (r >= 0) open_d = ts + r - open_st;
+      }
+    }
+    // 7. clear the bits this lane set, once every lane has read them
+    if (tile_bad) __syncthreads();
+    if (__builtin_expect(bad != 0, 0)) {
+      for (int u = 0; u < kU; ++u) {
+        if ((bad >> u) & 1) {
+          reinterpret_cast<uint16_t*>(regm)[u * 64 + lane] = 0;
+          reinterpret_cast<uint16_t*>(endm)[u * 64 + lane] = 0;
         }
       }
     }
@@ -262,28 +418,8 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     for (int u = 0; u < kU; ++u) x[u] = nx[u];
     __syncthreads();
   }
-}
-
-// Per string: first detection -> first-error offset; flags.
-__global__ void batch_finalize(BatchArgs a0, const BatchArgs* pa) {
-  const BatchArgs a = args_of(a0, pa);
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n; k += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t d = a.tmp[k];
-    if (d == kNoneRel) {
-      a.flags[k] = 1;
-      a.first_err[k] = -1;
-      continue;
-    }
-    const int64_t st = a.offsets[k];
-    const int64_t len = a.offsets[k + 1] - st;
-    auto byte_at = [&](int64_t q) -> uint32_t { return (q >= 0 && q < len) ? a.data[st + q] : 0u; };
-    int64_t s = d;
-    for (int64_t q = d; q >= 0 && q >= d - 3; --q) {
-      if (byte_at(q - 1) < 0xC0 && byte_at(q - 2) < 0xE0 && byte_at(q - 3) < 0xF0) { s = q; break; }
-    }
-    a.flags[k] = 0;
-    a.first_err[k] = s;
-  }
+  // the string still open runs into the next wave
+  if (open_k >= 0 && lane0) cross_wave(a, open_k, open_st, offsets[open_k + 1], open_d, c0, per);
 }
 
 __global__ void offsets_check(const int64_t* __restrict__ offsets, int64_t n, int* bad) {
@@ -300,30 +436,37 @@ hipError_t launch_offsets_check(const int64_t* offsets, int64_t n, int* bad, int
   return hipGetLastError();
 }
 
-static BatchArgs make_args(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* flags, int64_t* first_err) {
-  BatchArgs a;
-  a.data = data; a.offsets = offsets; a.n = n; a.lo = a.hi = a.c0 = 0;
-  a.flags = flags; a.first_err = first_err;
-  a.tmp = first_err;  // per-string detections are staged in the output array
-  return a;
+// Empty cross-wave slots: no arrivals, no partial detection.
+__global__ void batch_slots_init(unsigned long long* slot, int slots) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < slots; i += gridDim.x * blockDim.x) slot[i] = kSlotNone;
 }
 
-// The three kernels with fixed grids (grid-stride init/finalize, persistent main), so
-// the same launches serve any batch; pa (device) overrides a when not null.
-static hipError_t launch_batch_kernels(const BatchArgs& a, const BatchArgs* pa, const TuneBatch& cfg, int num_cus,
-                                       hipStream_t st) {
-  const int waves = num_cus * (cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1);
-  const int fin_blocks = num_cus * 8;
-  hipLaunchKernelGGL(batch_init, dim3(fin_blocks), dim3(256), 0, st, a, pa);
-  hipLaunchKernelGGL(batch_main, dim3(waves), dim3(64), 0, st, a, pa);
-  hipLaunchKernelGGL(batch_finalize, dim3(fin_blocks), dim3(256), 0, st, a, pa);
+hipError_t launch_batch_slots_init(unsigned long long* slot, int slots, hipStream_t st) {
+  hipLaunchKernelGGL(batch_slots_init, dim3((slots + 255) / 256), dim3(256), 0, st, slot, slots);
   return hipGetLastError();
 }
 
-hipError_t launch_batch(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* flags, int64_t* first_err,
-                        const TuneBatch& cfg, int num_cus, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  return launch_batch_kernels(make_args(data, offsets, n, flags, first_err), nullptr, cfg, num_cus, st);
+BatchArgs batch_args(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* flags, int64_t* first_err,
+                     unsigned long long* slot) {
+  BatchArgs a;
+  a.data = data; a.offsets = offsets; a.n = n;
+  a.slot = slot;
+  a.flags = flags; a.first_err = first_err;
+  return a;
+}
+
+// One persistent grid of one-wave workgroups (fixed shape, so the same launch
+// serves any batch); pa (device) overrides a when not null.
+static hipError_t launch_batch_kernels(const BatchArgs& a, const BatchArgs* pa, const TuneBatch& cfg, int num_cus,
+                                       hipStream_t st) {
+  const int waves = num_cus * (cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1);
+  hipLaunchKernelGGL(batch_main, dim3(waves), dim3(64), 0, st, a, pa);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchArgs& a, const TuneBatch& cfg, int num_cus, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  return launch_batch_kernels(a, nullptr, cfg, num_cus, st);
 }
 
 hipError_t capture_batch_graph(const BatchArgs* dparams, const TuneBatch& cfg, int num_cus, hipGraphExec_t* exec) {
@@ -333,7 +476,7 @@ hipError_t capture_batch_graph(const BatchArgs* dparams, const TuneBatch& cfg, i
   hipGraph_t graph = nullptr;
   e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    const BatchArgs dummy = make_args(nullptr, nullptr, 0, nullptr, nullptr);
+    const BatchArgs dummy = batch_args(nullptr, nullptr, 0, nullptr, nullptr, nullptr);
     hipError_t le = launch_batch_kernels(dummy, dparams, cfg, num_cus, cap);
     e = hipStreamEndCapture(cap, &graph);
     if (e == hipSuccess) e = le;
@@ -342,10 +485,6 @@ hipError_t capture_batch_graph(const BatchArgs* dparams, const TuneBatch& cfg, i
   if (graph) (void)hipGraphDestroy(graph);
   (void)hipStreamDestroy(cap);
   return e;
-}
-
-BatchArgs batch_args(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* flags, int64_t* first_err) {
-  return make_args(data, offsets, n, flags, first_err);
 }
 
 }  // namespace utf8v

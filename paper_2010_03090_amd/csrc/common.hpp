@@ -39,9 +39,7 @@ struct BatchArgs {
   const uint8_t* data;
   const int64_t* offsets;
   int64_t n;                  // strings
-  int64_t lo, hi;             // byte range [offsets[0], offsets[n]) (read on the device)
-  int64_t c0;                 // first chunk position (16-byte aligned address, <= lo)
-  int64_t* tmp;               // per-string first detection (relative), kNoneRel if none
+  unsigned long long* slot;   // workspace, one word per wave: arrivals and partial first detection
   uint8_t* flags;
   int64_t* first_err;
 };
@@ -62,10 +60,11 @@ __device__ __forceinline__ void wave_min_to(unsigned long long* dst, uint64_t v,
 
 hipError_t launch_single(const uint8_t* buf, uint64_t n, unsigned long long* dmin, int64_t* out,
                          const TuneSingle& cfg, int num_cus, hipStream_t st);
-hipError_t launch_batch(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* flags, int64_t* first_err,
-                        const TuneBatch& cfg, int num_cus, hipStream_t st);
+BatchArgs batch_args(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* flags, int64_t* first_err,
+                     unsigned long long* slot);
+hipError_t launch_batch(const BatchArgs& a, const TuneBatch& cfg, int num_cus, hipStream_t st);
+hipError_t launch_batch_slots_init(unsigned long long* slot, int slots, hipStream_t st);
 hipError_t capture_batch_graph(const BatchArgs* dparams, const TuneBatch& cfg, int num_cus, hipGraphExec_t* exec);
-BatchArgs batch_args(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* flags, int64_t* first_err);
 hipError_t launch_offsets_check(const int64_t* offsets, int64_t n, int* bad, int num_cus, hipStream_t st);
 hipError_t launch_classify(const uint8_t* buf, uint64_t n, uint8_t* sc, uint8_t* err, hipStream_t st);
 hipError_t launch_read_ceiling(const uint8_t* buf, uint64_t n, uint32_t* out, int num_cus, hipStream_t st);

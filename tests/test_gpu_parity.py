@@ -239,6 +239,31 @@ def test_batch_config3_heavy_tail(u8):
     assert np.array_equal(e_o[expected >= 0], expected[expected >= 0])
 
 
+def test_batch_strings_across_tiles_and_waves(u8):
+    """Strings that span several 4 KiB tiles and several waves, errors near every kind of edge."""
+    rng = np.random.default_rng(17)
+    lens = np.concatenate([[4095, 4096, 4097, 8191, 8192, 8193, 12289, 0, 1, 2, 3, 0, 0],
+                           rng.integers(0, 20, 300), rng.integers(4000, 70000, 60), [1_500_000, 2_000_003, 0, 5]])
+    rng.shuffle(lens)
+    variants = rng.choice(["mixed", "cjk", "emoji", "latin", "ascii"], lens.size).tolist()
+    old = u8.get_config()
+    try:
+        for seed, err in ((31, 0.5), (32, 0.05), (33, 1.0)):
+            data, offsets, expected = synth.batch_from_lengths(lens, variants, seed, err_frac=err, base=seed)
+            f_o, e_o = oracle.first_error_batch(data, offsets)
+            assert np.array_equal(e_o[expected >= 0], expected[expected >= 0])
+            td, to = dev(data), dev(offsets)
+            for waves in (1, 2, 5, 16, 64):
+                say(f"case: across waves seed {seed} batch_waves_per_cu {waves}")
+                u8.set_config(batch_waves_per_cu=waves)
+                flags, ferr = u8.validate_batch(td, to)
+                torch.cuda.synchronize()
+                assert np.array_equal(ferr.cpu().numpy(), e_o), (seed, waves)
+                assert np.array_equal(flags.cpu().numpy(), f_o), (seed, waves)
+    finally:
+        u8.set_config(**old)
+
+
 def test_batch_graph_replays(u8):
     """The captured-graph entry point: every replay, with eager work between them, equals the oracle."""
     cases = []
