@@ -61,6 +61,12 @@ def parse():
                     help="comma list of single-buffer variants (profiling runs restrict this)")
     ap.add_argument("--no-tail-copies", action="store_true", help="skip the copies with a tail error")
     ap.add_argument("--config", default="", help="launch overrides, e.g. unroll=4,waves_per_cu=24,ascii=1")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop part")
+    ap.add_argument("--serve-loads", default="10000,50000,200000", help="offered loads, requests/s")
+    ap.add_argument("--serve-requests", type=int, default=100_000, help="measured requests per load")
+    ap.add_argument("--serve-baseline-requests", type=int, default=20_000,
+                    help="measured requests per load for one synchronous launch per request")
+    ap.add_argument("--serve-pool", type=int, default=256, help="distinct pre-generated requests")
     return ap.parse_args()
 
 
@@ -93,6 +99,10 @@ def main():
     # ---- batched: 1M log-normal strings vs one launch per string ------------------------------
     if not args.no_batch:
         result["batched"] = bench_batch(u8, lib, synth, torch, dev, stream, sh, args)
+
+    # ---- serving: continuous batching under Poisson load vs one launch per request -----------
+    if not args.no_serve:
+        result["serving"] = bench_serving(synth, args)
 
     # ---- CPU oracle on a bounded sample (1 core, as the paper's single thread) -----------------
     if not args.no_cpu and "random" in host and len(host) > 1:
@@ -373,6 +383,70 @@ def bench_graph(u8, lib, torch, td, to, flags, ferr, nstr, offsets, expected, st
                 raise SystemExit(f"wrong {name} small-batch result")
         out[f"n{n}"] = row
     return out
+
+
+def bench_serving(synth, args):
+    """Open-loop Poisson arrivals; each request 1..4096 strings shaped like the 1M-string batch.
+
+    Payloads are pre-generated in pinned host memory (a pool of distinct requests,
+    replayed); host-to-device copies are inside the measured latency.  Latency =
+    results on the host - scheduled arrival.  1 s of warm-up arrivals precede the
+    measured ones at each load.
+    """
+    import oracle
+    from paper_2010_03090_amd import serve
+    t0 = time.time()
+    rng = np.random.default_rng(2024)
+    pool, expect, bytes_, strings_ = [], [], [], []
+    for i in range(args.serve_pool):
+        m = int(rng.integers(1, 4097))
+        lens = synth.lengths(m, "lognormal", 64, 1.2, 1, 65536, 7000 + i)
+        data, offsets, _ = synth.batch_from_lengths(lens, "mixed", 9000 + i, err_frac=0.01)
+        pool.append(serve.Request(data, offsets))
+        expect.append(oracle.first_error_batch(data, offsets))
+        bytes_.append(int(offsets[-1]))
+        strings_.append(m)
+    bytes_, strings_ = np.array(bytes_), np.array(strings_)
+    log(f"serving pool ready in {time.time() - t0:.1f}s: {len(pool)} requests, mean {bytes_.mean() / 1e3:.0f} KB, "
+        f"{strings_.mean():.0f} strings")
+    loads = []
+    for li, rate in enumerate(int(x) for x in args.serve_loads.split(",")):
+        row = {"offered_req_per_s": rate, "offered_GBps": round(rate * bytes_.mean() / 1e9, 2)}
+        for mode, name, nmeas in ((serve.MODE_SERVER, "continuous_batching", args.serve_requests),
+                                  (serve.MODE_PER_REQUEST, "per_request_launch", args.serve_baseline_requests)):
+            nwarm = int(min(rate * 1.0, nmeas))
+            n = nwarm + nmeas
+            arrivals = serve.poisson_arrivals(rate, n, 100 + li)
+            picks = np.random.default_rng(200 + li).integers(0, len(pool), n)
+            for r in pool:
+                r.reset()
+            t1 = time.time()
+            lat, span = serve.replay(pool, arrivals, picks, mode)
+            for k in set(picks.tolist()):
+                f, e = pool[k].results()
+                if not (np.array_equal(e, expect[k][1]) and np.array_equal(f, expect[k][0])):
+                    raise SystemExit(f"wrong serving result ({name}, load {rate}, request {k})")
+            m_lat = lat[nwarm:] / 1e3
+            mp = picks[nwarm:]
+            # measured window: first measured arrival to last completion
+            win = (arrivals[-1] - arrivals[nwarm] + lat[-1]) / 1e9
+            done_bytes = float(bytes_[mp].sum())
+            row[name] = {"p50_us": round(float(np.percentile(m_lat, 50)), 1),
+                         "p99_us": round(float(np.percentile(m_lat, 99)), 1),
+                         "mean_us": round(float(m_lat.mean()), 1),
+                         "achieved_req_per_s": round(nmeas / win),
+                         "GBps": round(done_bytes / win / 1e9, 2),
+                         "strings_per_s": round(float(strings_[mp].sum()) / win),
+                         "requests": nmeas, "warmup_requests": nwarm}
+            log(f"serving {name} at {rate}/s: p50 {row[name]['p50_us']} us, p99 {row[name]['p99_us']} us, "
+                f"{row[name]['GBps']} GB/s ({time.time() - t1:.1f}s)")
+        loads.append(row)
+    return {"workload": "Poisson arrivals; each request 1..4096 strings (uniform), log-normal lengths "
+                        "(median 64 B, sigma 1.2), mixed code points, 1% injected errors; payloads in pinned "
+                        "host memory, copies included",
+            "admission_budget_bytes": int(serve.default_config().budget_bytes),
+            "pool_requests": len(pool), "mean_request_bytes": round(float(bytes_.mean())),
+            "loads": loads}
 
 
 def cpu_baseline(host, n, seconds):

@@ -110,6 +110,87 @@ int utf8v_validate_batch_graph(const uint8_t *data, const int64_t *offsets, int6
  */
 int utf8v_check_offsets(const int64_t *offsets, int64_t n, void *stream);
 
+/* ---- serving: continuous batching of requests ---------------------------------------- */
+
+/*
+ * A server validates requests -- each one a CSR batch of strings, with the
+ * semantics of utf8_validate_batch -- submitted at any time from any thread.  A
+ * scheduler thread admits pending requests in submission order into a device ring
+ * of budget_bytes and launches them together as one batch as soon as one of
+ * max_inflight batch slots is free (continuous batching; consecutive batches use
+ * alternating streams and overlap on the GPU).  Per batch it copies the payloads
+ * and offsets straight from the requests' pinned host memory into the ring,
+ * validates them in one launch and writes every request's results back into its
+ * host arrays.  A request's results do not depend on what it is batched with.
+ */
+typedef struct {
+  uint64_t budget_bytes;      /* device ring (admission budget), default 8 GiB */
+  uint64_t max_batch_bytes;   /* payload bytes per batch (and per request), default 64 MiB */
+  int64_t max_batch_strings;  /* strings per batch incl. one separator per request, default 4 Mi */
+  int32_t max_batch_requests; /* requests per batch, default 4096 */
+  int32_t max_inflight;       /* batches on the GPU at once, 1..64, default 4 */
+  int32_t streams;            /* streams the batches alternate over, 1..8, default 2 */
+  int32_t max_pending;        /* submitted but unfinished requests, default 262144 */
+} utf8v_server_config;
+
+typedef struct utf8v_server utf8v_server;
+
+/* Fill *cfg with the defaults above. */
+int utf8v_server_default_config(utf8v_server_config *cfg);
+
+/*
+ * Create a server on the current device (allocates the ring, pinned staging and
+ * streams; starts the scheduler thread).  UTF8V_EINVAL if a limit is out of range
+ * or the budget cannot hold the largest batch the limits allow.
+ */
+int utf8v_server_create(const utf8v_server_config *cfg, utf8v_server **out);
+
+/*
+ * Submit one request: strings data[offsets[k] .. offsets[k+1]), k < n.  offsets
+ * (n+1 entries) must be pinned host memory (read by the host and the GPU); data,
+ * out_flags and out_first_err pinned host or device memory.  All four must stay
+ * valid until the request is done.  Results: as utf8_validate_batch.  *ticket
+ * identifies the request.  Blocks only while max_pending requests are unfinished.
+ * UTF8V_EINVAL for a request larger than the batch limits.
+ */
+int utf8v_server_submit(utf8v_server *srv, const uint8_t *data, const int64_t *offsets, int64_t n,
+                        uint8_t *out_flags, int64_t *out_first_err, uint64_t *ticket);
+
+/*
+ * 1 if the request is done (its results are in place; *done_ns, if not NULL,
+ * gets the utf8v_clock_ns() time it was seen done), 0 if not yet, < 0 on error.
+ */
+int utf8v_server_poll(utf8v_server *srv, uint64_t ticket, int64_t *done_ns);
+
+/* Wait until the request is done; as poll otherwise (returns UTF8V_OK when done). */
+int utf8v_server_wait(utf8v_server *srv, uint64_t ticket, int64_t *done_ns);
+
+/* out4 = {requests done, batches launched, largest batch (requests), ring bytes}. */
+int utf8v_server_stats(utf8v_server *srv, int64_t *out4);
+
+/* Finish every submitted request, stop the scheduler and free everything. */
+int utf8v_server_destroy(utf8v_server *srv);
+
+/* Monotonic clock used for done times, in nanoseconds. */
+int64_t utf8v_clock_ns(void);
+
+/*
+ * utf8v_serve_replay -- open-loop load generator for measurements.  Request i
+ * (nreq of them, arrival_ns non-decreasing, relative to the start) is pool entry
+ * pick[i] of npool requests given as parallel arrays (pinned host memory as for
+ * utf8v_server_submit).  It is submitted at its arrival time, whether or not
+ * earlier requests are done, and latency_ns[i] = (time its results are on the
+ * host) - (its arrival time).  mode 0: through a server made with cfg;
+ * mode 1: one synchronous launch per request, in arrival order (copy in,
+ * validate, copy out, wait).  *span_ns (may be NULL) = last completion - first
+ * arrival.  Results land in the pool's result arrays (the same values for every
+ * repetition of an entry).
+ */
+int utf8v_serve_replay(const utf8v_server_config *cfg, int mode, const uint8_t *const *req_data,
+                       const int64_t *const *req_offsets, const int64_t *req_n, uint8_t *const *req_flags,
+                       int64_t *const *req_errs, int npool, const int64_t *arrival_ns, const int32_t *pick,
+                       int64_t nreq, int64_t *latency_ns, int64_t *span_ns);
+
 /* ---- tuning (see utf8v_tune_* in the Python package for the autotuner) ------------ */
 
 typedef struct {

@@ -30,6 +30,18 @@ class Config(ctypes.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_batch_bytes", ctypes.c_uint64),
+                ("max_batch_strings", ctypes.c_int64), ("max_batch_requests", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("streams", ctypes.c_int32), ("max_pending", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+_u64 = ctypes.c_uint64
+_pcfg = ctypes.POINTER(ServerConfig)
+
 SIGNATURES = {
     "utf8_validate": (ctypes.c_bool, [_vp, _sz]),
     "utf8v_validate_ex": (_i32, [_vp, _sz, _vp, _vp]),
@@ -48,6 +60,15 @@ SIGNATURES = {
     "utf8v_last_hip_error": (_i32, []),
     "utf8v_num_cus": (_i32, []),
     "utf8v_release": (_i32, []),
+    "utf8v_server_default_config": (_i32, [_pcfg]),
+    "utf8v_server_create": (_i32, [_pcfg, ctypes.POINTER(_vp)]),
+    "utf8v_server_submit": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, ctypes.POINTER(_u64)]),
+    "utf8v_server_poll": (_i32, [_vp, _u64, ctypes.POINTER(_i64)]),
+    "utf8v_server_wait": (_i32, [_vp, _u64, ctypes.POINTER(_i64)]),
+    "utf8v_server_stats": (_i32, [_vp, _vp]),
+    "utf8v_server_destroy": (_i32, [_vp]),
+    "utf8v_clock_ns": (_i64, []),
+    "utf8v_serve_replay": (_i32, [_pcfg, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _i64, _vp, _vp]),
 }
 
 _lib = None

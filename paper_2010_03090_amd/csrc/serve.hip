@@ -1,0 +1,598 @@
+// Serving loop: continuous batching of validation requests on one GPU.
+//
+// Clients submit requests (a CSR batch of strings in pinned host memory) at any
+// time.  One scheduler thread admits pending requests, in arrival order, into a
+// device ring of a fixed byte budget, and launches them as one batch as soon as a
+// batch slot is free, so requests that arrive while others are on the GPU join
+// the next batch and batches overlap on alternating streams.  Per batch, on its
+// stream:
+//   1. the descriptor table (and its lookup tables) is copied to the ring;
+//   2. serve_gather reads the payloads and offsets straight from pinned host
+//      memory into the ring, rebasing the offsets so the requests form one CSR
+//      batch (a padding string separates consecutive requests);
+//   3. the batch validator (one launch) runs over it;
+//   4. serve_scatter writes each request's flags and first-error offsets back
+//      into its pinned host result arrays;
+//   5. an event marks the batch; the scheduler retires batches in order, stamps
+//      their requests done and releases their ring space.
+// A string's result depends only on its own bytes (each string is its own
+// stream), so a request's results are the same alone and in any mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <deque>
+#include <memory>
+#include <thread>
+#include <vector>
+
+#include "../../include/utf8v.h"
+#include "common.hpp"
+#include "serve_core.hpp"
+
+namespace utf8v {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// One request of a batch as the gather / scatter kernels see it.
+struct ServeDesc {
+  const uint8_t* src;      // payload: bytes [0, bytes) (device-accessible host memory)
+  const int64_t* src_off;  // its n+1 offsets; src_off[0] is the payload start
+  uint8_t* dst_flags;      // n results
+  int64_t* dst_err;
+  int64_t n;
+  int64_t bytes;
+  int64_t data_off;  // payload start in the batch data region
+  int64_t str_off;   // index of its first string in the batch
+};
+
+constexpr int kGatherChunk = 4096;  // payload bytes per gather workgroup (16 per thread)
+constexpr int kStringBlock = 256;   // strings per offsets / scatter workgroup
+
+// Payload chunks first, then offset blocks.  chunk_req[c] / block_req[b] name the
+// first request overlapping payload chunk c / string block b.
+__global__ __launch_bounds__(256) void serve_gather(const ServeDesc* __restrict__ d, int nreq,
+                                                    const int32_t* __restrict__ chunk_req,
+                                                    const int32_t* __restrict__ block_req, int64_t chunks,
+                                                    uint8_t* __restrict__ data, int64_t data_end,
+                                                    int64_t* __restrict__ offs, int64_t strings) {
+  const int64_t b = blockIdx.x;
+  if (b < chunks) {
+    const int64_t p = b * kGatherChunk + threadIdx.x * 16;  // this thread's 16-byte word of the data region
+    if (p >= data_end) return;
+    for (int r = chunk_req[b]; r < nreq && d[r].data_off < p + 16; ++r) {
+      const int64_t s0 = d[r].data_off, s1 = s0 + d[r].bytes;
+      if (s1 <= p) continue;
+      if (s0 <= p && p + 16 <= s1) {  // whole word inside the payload: same alignment on both sides
+        *reinterpret_cast<u32x4*>(data + p) = *reinterpret_cast<const u32x4*>(d[r].src + (p - s0));
+      } else {
+        const int64_t a = p > s0 ? p : s0, e = p + 16 < s1 ? p + 16 : s1;
+        for (int64_t q = a; q < e; ++q) data[q] = d[r].src[q - s0];
+      }
+    }
+    return;
+  }
+  const int64_t e = (b - chunks) * kStringBlock + threadIdx.x;  // boundary index
+  if (e > strings) return;
+  if (e == strings) {  // end of the last payload
+    offs[e] = d[nreq - 1].data_off + d[nreq - 1].bytes;
+    return;
+  }
+  int r = block_req[b - chunks];
+  while (r + 1 < nreq && d[r + 1].str_off <= e) ++r;
+  const int64_t k = e - d[r].str_off;  // k <= n: boundary k of request r (k == n: its padding string)
+  offs[e] = k < d[r].n ? d[r].data_off + (d[r].src_off[k] - d[r].src_off[0]) : d[r].data_off + d[r].bytes;
+}
+
+__global__ __launch_bounds__(256) void serve_scatter(const ServeDesc* __restrict__ d, int nreq,
+                                                     const int32_t* __restrict__ block_req,
+                                                     const uint8_t* __restrict__ flags,
+                                                     const int64_t* __restrict__ errs, int64_t strings) {
+  const int64_t e = (int64_t)blockIdx.x * kStringBlock + threadIdx.x;
+  if (e >= strings) return;
+  int r = block_req[blockIdx.x];
+  while (r + 1 < nreq && d[r + 1].str_off <= e) ++r;
+  const int64_t k = e - d[r].str_off;
+  if (k < d[r].n) {
+    d[r].dst_flags[k] = flags[e];
+    d[r].dst_err[k] = errs[e];
+  }
+}
+
+}  // namespace utf8v
+
+namespace {
+
+using namespace utf8v;
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+struct Slot {  // one submitted request
+  const uint8_t* data;
+  const int64_t* offsets;
+  int64_t n, bytes;
+  uint8_t* flags;
+  int64_t* errs;
+  int64_t submit_ns, done_ns;
+  std::atomic<int> state{0};  // 0 free, 1 submitted, 2 scheduled, 3 done
+};
+
+struct Staging {  // pinned host image of one batch's descriptor region
+  uint8_t* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool busy = false;
+};
+
+struct InFlight {
+  uint64_t first, count;
+  int staging;
+};
+
+}  // namespace
+
+struct utf8v_server {
+  utf8v_server_config cfg;
+  int dev = 0, cus = 1;
+  std::vector<hipStream_t> streams;
+  std::vector<unsigned long long*> wave_slots;  // per stream: cross-wave slots of the batch kernel
+  uint8_t* ring = nullptr;
+  ByteRing alloc{0};
+  std::vector<Staging> staging;
+  std::unique_ptr<Slot[]> slots;
+  std::atomic<uint64_t> next_ticket{0};
+  std::atomic<uint64_t> retired{0};  // tickets below this are done
+  uint64_t sched = 0;                // next ticket to schedule
+  std::deque<InFlight> inflight;
+  std::atomic<bool> stop{false};
+  std::atomic<int> error{0};
+  std::thread worker;
+  int next_stream = 0;
+  // statistics
+  std::atomic<int64_t> batches{0}, max_batch{0};
+
+  Slot& slot(uint64_t t) { return slots[t % (uint64_t)cfg.max_pending]; }
+  void run();
+  bool launch_batch_of(uint64_t first, uint64_t count);
+  bool retire_ready();
+};
+
+namespace {
+
+// Table sizes in the descriptor region of a batch.
+size_t desc_region_bytes(size_t nreq, uint64_t data_bytes, int64_t strings) {
+  const size_t chunks = (size_t)((data_bytes + kGatherChunk - 1) / kGatherChunk) + 1;
+  const size_t blocks = (size_t)((strings + 1 + kStringBlock - 1) / kStringBlock) + 1;
+  return align_up(sizeof(ServeDesc) * nreq, 256) + align_up(4 * chunks, 256) + align_up(4 * blocks, 256);
+}
+
+// Ring bytes of the largest batch the limits allow.
+uint64_t max_footprint(const utf8v_server_config& c) {
+  const uint64_t r = (uint64_t)c.max_batch_requests, sn = (uint64_t)c.max_batch_strings + r;
+  const uint64_t data = c.max_batch_bytes + 16 * r;
+  return align_up(desc_region_bytes((size_t)r, data, (int64_t)sn), kRingAlign) + align_up(data + 16, kRingAlign) +
+         align_up(8 * (sn + 1), kRingAlign) + align_up(sn, kRingAlign) + align_up(8 * sn, kRingAlign);
+}
+
+}  // namespace
+
+bool utf8v_server::retire_ready() {
+  bool any = false;
+  while (!inflight.empty()) {
+    const InFlight& f = inflight.front();
+    const hipError_t q = hipEventQuery(staging[f.staging].ev);
+    if (q == hipErrorNotReady) break;
+    if (q != hipSuccess) {
+      error.store(UTF8V_EHIP);
+      (void)hipGetLastError();
+    }
+    const int64_t t = now_ns();
+    for (uint64_t i = 0; i < f.count; ++i) {
+      Slot& s = slot(f.first + i);
+      s.done_ns = t;
+      s.state.store(3, std::memory_order_release);
+    }
+    retired.store(f.first + f.count, std::memory_order_release);
+    staging[f.staging].busy = false;
+    alloc.release_oldest();
+    inflight.pop_front();
+    any = true;
+  }
+  return any;
+}
+
+// Plan, stage and enqueue tickets [first, first+count) as one batch.  False if the
+// ring or a staging buffer is not free yet (nothing is enqueued then).
+bool utf8v_server::launch_batch_of(uint64_t first, uint64_t count) {
+  int si = -1;
+  for (size_t i = 0; i < staging.size(); ++i)
+    if (!staging[i].busy) { si = (int)i; break; }
+  if (si < 0) return false;
+  std::vector<PlanRequest> reqs(count);
+  for (uint64_t i = 0; i < count; ++i) {
+    const Slot& s = slot(first + i);
+    reqs[i] = PlanRequest{(uint64_t)s.bytes, s.n, reinterpret_cast<uintptr_t>(s.data + s.offsets[0])};
+  }
+  BatchPlan plan = plan_batch(reqs, 0, count, sizeof(ServeDesc));
+  const size_t dbytes = desc_region_bytes(count, plan.data_bytes, plan.strings);
+  // the descriptor region replaces the plan's descriptor table
+  const uint64_t shift = align_up(dbytes, kRingAlign) - plan.data_at;
+  plan.data_at += shift; plan.offsets_at += shift; plan.flags_at += shift; plan.errs_at += shift; plan.total += shift;
+  Staging& stg = staging[si];
+  if (dbytes > stg.cap) {
+    error.store(UTF8V_ENOMEM);
+    return false;
+  }
+  const int64_t at = alloc.reserve(plan.total);
+  if (at < 0) return false;
+  uint8_t* base = ring + at;
+  // descriptor region image
+  ServeDesc* desc = reinterpret_cast<ServeDesc*>(stg.host);
+  const size_t chunks = (size_t)((plan.data_bytes + kGatherChunk - 1) / kGatherChunk);
+  const size_t blocks = (size_t)((plan.strings + 1 + kStringBlock - 1) / kStringBlock);
+  int32_t* chunk_req = reinterpret_cast<int32_t*>(stg.host + align_up(sizeof(ServeDesc) * count, 256));
+  int32_t* block_req = reinterpret_cast<int32_t*>(reinterpret_cast<uint8_t*>(chunk_req) +
+                                                  align_up(4 * (chunks + 1), 256));
+  for (uint64_t i = 0; i < count; ++i) {
+    const Slot& s = slot(first + i);
+    desc[i] = ServeDesc{s.data + s.offsets[0], s.offsets, s.flags, s.errs, s.n, s.bytes,
+                        (int64_t)plan.data_off[i], plan.str_off[i]};
+  }
+  {  // first request overlapping each payload chunk / string block
+    size_t r = 0;
+    for (size_t c = 0; c < chunks; ++c) {
+      const uint64_t lo = (uint64_t)c * kGatherChunk;
+      while (r + 1 < count && plan.data_off[r] + reqs[r].bytes <= lo) ++r;
+      chunk_req[c] = (int32_t)r;
+    }
+    r = 0;
+    for (size_t b = 0; b < blocks; ++b) {
+      const int64_t lo = (int64_t)b * kStringBlock;
+      while (r + 1 < count && plan.str_off[r + 1] <= lo) ++r;
+      block_req[b] = (int32_t)r;
+    }
+  }
+  hipStream_t st = streams[next_stream];
+  unsigned long long* wslots = wave_slots[next_stream];
+  next_stream = (next_stream + 1) % (int)streams.size();
+  const ServeDesc* ddesc = reinterpret_cast<const ServeDesc*>(base);
+  const int32_t* dchunk = reinterpret_cast<const int32_t*>(base + (reinterpret_cast<uint8_t*>(chunk_req) - stg.host));
+  const int32_t* dblock = reinterpret_cast<const int32_t*>(base + (reinterpret_cast<uint8_t*>(block_req) - stg.host));
+  uint8_t* data = base + plan.data_at;
+  int64_t* offs = reinterpret_cast<int64_t*>(base + plan.offsets_at);
+  uint8_t* flags = base + plan.flags_at;
+  int64_t* errs = reinterpret_cast<int64_t*>(base + plan.errs_at);
+  const size_t used = (reinterpret_cast<uint8_t*>(block_req) - stg.host) + 4 * blocks;
+  hipError_t e = hipMemcpyAsync(base, stg.host, used, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    const int64_t grid = (int64_t)chunks + (int64_t)blocks;
+    hipLaunchKernelGGL(serve_gather, dim3((unsigned)grid), dim3(256), 0, st, ddesc, (int)count, dchunk, dblock,
+                       (int64_t)chunks, data, (int64_t)plan.data_bytes, offs, plan.strings);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    TuneBatch tb;
+    utf8v_config c;
+    utf8v_get_config(&c);
+    tb.waves_per_cu = c.batch_waves_per_cu;
+    e = utf8v::launch_batch(batch_args(data, offs, plan.strings, flags, errs, wslots), tb, cus, st);
+  }
+  if (e == hipSuccess) {
+    const int64_t sblocks = (plan.strings + kStringBlock - 1) / kStringBlock;
+    if (sblocks > 0) {
+      hipLaunchKernelGGL(serve_scatter, dim3((unsigned)sblocks), dim3(256), 0, st, ddesc, (int)count, dblock, flags,
+                         errs, plan.strings);
+      e = hipGetLastError();
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(stg.ev, st);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    error.store(UTF8V_EHIP);
+    // nothing more runs on this server; the batch is retired when its event reports
+  }
+  stg.busy = true;
+  for (uint64_t i = 0; i < count; ++i) slot(first + i).state.store(2, std::memory_order_relaxed);
+  inflight.push_back(InFlight{first, count, si});
+  batches.fetch_add(1);
+  int64_t m = max_batch.load();
+  while ((int64_t)count > m && !max_batch.compare_exchange_weak(m, (int64_t)count)) {
+  }
+  return true;
+}
+
+void utf8v_server::run() {
+  (void)hipSetDevice(dev);
+  const uint64_t max_req = (uint64_t)cfg.max_batch_requests;
+  for (;;) {
+    bool progress = retire_ready();
+    if ((int)inflight.size() < cfg.max_inflight) {
+      // admit submitted requests in ticket order up to the batch limits
+      uint64_t count = 0, bytes = 0;
+      int64_t strings = 0;
+      while (count < max_req) {
+        Slot& s = slot(sched + count);
+        if (sched + count >= next_ticket.load(std::memory_order_acquire)) break;
+        if (s.state.load(std::memory_order_acquire) != 1) break;
+        if (count > 0 && (bytes + (uint64_t)s.bytes > cfg.max_batch_bytes ||
+                          strings + s.n + 1 > cfg.max_batch_strings))
+          break;
+        bytes += (uint64_t)s.bytes;
+        strings += s.n + 1;
+        ++count;
+      }
+      if (count > 0 && launch_batch_of(sched, count)) {
+        sched += count;
+        progress = true;
+      }
+    }
+    if (stop.load(std::memory_order_acquire) && inflight.empty() &&
+        sched >= next_ticket.load(std::memory_order_acquire))
+      break;
+    if (!progress) std::this_thread::yield();
+  }
+}
+
+namespace {
+
+thread_local int g_serve_status = UTF8V_OK;
+
+int fail(int s) { g_serve_status = s; return s; }
+
+bool device_accessible(const void* p) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type != hipMemoryTypeUnregistered;
+}
+
+bool host_readable(const void* p) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeHost || attr.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+extern "C" {
+
+int utf8v_server_default_config(utf8v_server_config* cfg) {
+  if (!cfg) return UTF8V_EINVAL;
+  cfg->budget_bytes = 8ull << 30;
+  cfg->max_batch_bytes = 64ull << 20;
+  cfg->max_batch_strings = 4ll << 20;
+  cfg->max_batch_requests = 4096;
+  cfg->max_inflight = 4;
+  cfg->streams = 2;
+  cfg->max_pending = 1 << 18;
+  return UTF8V_OK;
+}
+
+int utf8v_server_create(const utf8v_server_config* cfg, utf8v_server** out) {
+  if (!cfg || !out) return UTF8V_EINVAL;
+  if (cfg->max_batch_bytes == 0 || cfg->max_batch_strings < 1 || cfg->max_batch_requests < 1 ||
+      cfg->max_inflight < 1 || cfg->max_inflight > 64 || cfg->streams < 1 || cfg->streams > 8 ||
+      cfg->max_pending < 1 || cfg->budget_bytes < max_footprint(*cfg))
+    return UTF8V_EINVAL;
+  std::unique_ptr<utf8v_server> s(new utf8v_server);
+  s->cfg = *cfg;
+  hipError_t e = hipGetDevice(&s->dev);
+  if (e != hipSuccess) return UTF8V_EHIP;
+  s->cus = utf8v_num_cus() > 0 ? utf8v_num_cus() : 1;
+  s->alloc = ByteRing(cfg->budget_bytes);
+  s->slots.reset(new Slot[(size_t)cfg->max_pending]);
+  e = hipMalloc(&s->ring, s->alloc.capacity());
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? UTF8V_ENOMEM : UTF8V_EHIP;
+  const size_t scap = desc_region_bytes((size_t)cfg->max_batch_requests,
+                                        cfg->max_batch_bytes + 16ull * (uint64_t)cfg->max_batch_requests,
+                                        cfg->max_batch_strings + cfg->max_batch_requests);
+  s->staging.resize((size_t)cfg->max_inflight);
+  for (auto& st : s->staging) {
+    e = hipHostMalloc(&st.host, scap, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&st.ev, hipEventDisableTiming);
+    if (e != hipSuccess) break;
+    st.cap = scap;
+  }
+  for (int i = 0; e == hipSuccess && i < cfg->streams; ++i) {
+    hipStream_t st = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) break;
+    s->streams.push_back(st);
+    unsigned long long* ws = nullptr;
+    const int n = s->cus * 64;  // one word per possible wave of the batch grid
+    e = hipMalloc(&ws, sizeof(unsigned long long) * n);
+    if (e != hipSuccess) break;
+    s->wave_slots.push_back(ws);
+    e = utf8v::launch_batch_slots_init(ws, n, st);
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    utf8v_server_destroy(s.release());
+    return UTF8V_EHIP;
+  }
+  utf8v_server* raw = s.release();
+  raw->worker = std::thread([raw] { raw->run(); });
+  *out = raw;
+  return UTF8V_OK;
+}
+
+int utf8v_server_submit(utf8v_server* s, const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* out_flags,
+                        int64_t* out_first_err, uint64_t* ticket) {
+  if (!s || !offsets || n < 0 || !ticket) return fail(UTF8V_EINVAL);
+  if (n > 0 && (!out_flags || !out_first_err)) return fail(UTF8V_EINVAL);
+  if (!host_readable(offsets)) return fail(UTF8V_ENOTDEVICE);
+  const int64_t bytes = offsets[n] - offsets[0];
+  if (offsets[0] < 0 || bytes < 0) return fail(UTF8V_EINVAL);
+  if (bytes > 0 && !data) return fail(UTF8V_EINVAL);
+  if ((bytes > 0 && !device_accessible(data)) || (n > 0 && (!device_accessible(out_flags) ||
+                                                             !device_accessible(out_first_err))))
+    return fail(UTF8V_ENOTDEVICE);
+  if ((uint64_t)bytes > s->cfg.max_batch_bytes || n + 1 > s->cfg.max_batch_strings) return fail(UTF8V_EINVAL);
+  if (s->error.load()) return fail(s->error.load());
+  const uint64_t t = s->next_ticket.fetch_add(1);
+  while (t - s->retired.load(std::memory_order_acquire) >= (uint64_t)s->cfg.max_pending) std::this_thread::yield();
+  Slot& sl = s->slot(t);
+  while (sl.state.load(std::memory_order_acquire) == 1 || sl.state.load(std::memory_order_acquire) == 2)
+    std::this_thread::yield();
+  sl.data = data;
+  sl.offsets = offsets;
+  sl.n = n;
+  sl.bytes = bytes;
+  sl.flags = out_flags;
+  sl.errs = out_first_err;
+  sl.submit_ns = now_ns();
+  sl.done_ns = 0;
+  sl.state.store(1, std::memory_order_release);
+  *ticket = t;
+  return UTF8V_OK;
+}
+
+int utf8v_server_poll(utf8v_server* s, uint64_t ticket, int64_t* done_ns) {
+  if (!s) return UTF8V_EINVAL;
+  if (ticket >= s->retired.load(std::memory_order_acquire)) return s->error.load() ? s->error.load() : 0;
+  if (done_ns) *done_ns = s->slot(ticket).done_ns;
+  return 1;
+}
+
+int utf8v_server_wait(utf8v_server* s, uint64_t ticket, int64_t* done_ns) {
+  if (!s || ticket >= s->next_ticket.load()) return UTF8V_EINVAL;
+  for (;;) {
+    const int r = utf8v_server_poll(s, ticket, done_ns);
+    if (r != 0) return r < 0 ? r : UTF8V_OK;
+    std::this_thread::yield();
+  }
+}
+
+int utf8v_server_stats(utf8v_server* s, int64_t* out4) {
+  if (!s || !out4) return UTF8V_EINVAL;
+  out4[0] = (int64_t)s->retired.load();
+  out4[1] = s->batches.load();
+  out4[2] = s->max_batch.load();
+  out4[3] = (int64_t)s->alloc.capacity();
+  return UTF8V_OK;
+}
+
+int utf8v_server_destroy(utf8v_server* s) {
+  if (!s) return UTF8V_EINVAL;
+  s->stop.store(true, std::memory_order_release);
+  if (s->worker.joinable()) s->worker.join();
+  for (auto st : s->streams) (void)hipStreamSynchronize(st);
+  for (auto& st : s->staging) {
+    if (st.ev) (void)hipEventDestroy(st.ev);
+    if (st.host) (void)hipHostFree(st.host);
+  }
+  for (auto p : s->wave_slots) (void)hipFree(p);
+  for (auto st : s->streams) (void)hipStreamDestroy(st);
+  if (s->ring) (void)hipFree(s->ring);
+  const int err = s->error.load();
+  delete s;
+  return err;
+}
+
+int64_t utf8v_clock_ns(void) { return now_ns(); }
+
+int utf8v_serve_replay(const utf8v_server_config* cfg, int mode, const uint8_t* const* req_data,
+                       const int64_t* const* req_offsets, const int64_t* req_n, uint8_t* const* req_flags,
+                       int64_t* const* req_errs, int npool, const int64_t* arrival_ns, const int32_t* pick,
+                       int64_t nreq, int64_t* latency_ns, int64_t* span_ns) {
+  if (!cfg || !req_data || !req_offsets || !req_n || !req_flags || !req_errs || npool < 1 || !arrival_ns || !pick ||
+      nreq < 1 || !latency_ns || (mode != 0 && mode != 1))
+    return UTF8V_EINVAL;
+  for (int64_t i = 0; i < nreq; ++i)
+    if (pick[i] < 0 || pick[i] >= npool || (i > 0 && arrival_ns[i] < arrival_ns[i - 1])) return UTF8V_EINVAL;
+  auto wait_until = [](int64_t t) {
+    while (now_ns() < t) {
+    }
+  };
+  if (mode == 0) {  // continuous batching server
+    utf8v_server* srv = nullptr;
+    int rc = utf8v_server_create(cfg, &srv);
+    if (rc) return rc;
+    std::vector<uint64_t> tickets((size_t)nreq);
+    std::atomic<int64_t> published{0};
+    std::atomic<int> werr{0};
+    const int64_t t0 = now_ns() + 2000000;
+    std::thread collector([&] {
+      for (int64_t i = 0; i < nreq; ++i) {
+        while (published.load(std::memory_order_acquire) <= i) std::this_thread::yield();
+        int64_t done = 0;
+        const int r = utf8v_server_wait(srv, tickets[(size_t)i], &done);
+        if (r) { werr.store(r); done = now_ns(); }
+        latency_ns[i] = done - (t0 + arrival_ns[i]);
+        if (span_ns && i == nreq - 1) *span_ns = done - (t0 + arrival_ns[0]);
+      }
+    });
+    for (int64_t i = 0; i < nreq && !rc; ++i) {
+      wait_until(t0 + arrival_ns[i]);
+      const int k = pick[i];
+      rc = utf8v_server_submit(srv, req_data[k], req_offsets[k], req_n[k], req_flags[k], req_errs[k],
+                               &tickets[(size_t)i]);
+      if (!rc) published.store(i + 1, std::memory_order_release);
+    }
+    if (rc) {  // let the collector finish on what was submitted
+      const int64_t done_count = published.load();
+      for (int64_t i = done_count; i < nreq; ++i) latency_ns[i] = -1;
+      published.store(INT64_MAX);
+    }
+    collector.join();
+    const int d = utf8v_server_destroy(srv);
+    return rc ? rc : (werr.load() ? werr.load() : d);
+  }
+  // one synchronous launch per request, first come first served
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return UTF8V_EHIP;
+  const int cus = utf8v_num_cus() > 0 ? utf8v_num_cus() : 1;
+  int64_t max_b = 0, max_n = 0;
+  for (int k = 0; k < npool; ++k) {
+    max_b = std::max(max_b, req_offsets[k][req_n[k]] - req_offsets[k][0]);
+    max_n = std::max(max_n, req_n[k]);
+  }
+  uint8_t *dd = nullptr, *df = nullptr;
+  int64_t *doff = nullptr, *de = nullptr;
+  unsigned long long* ws = nullptr;
+  hipStream_t st = nullptr;
+  hipError_t e = hipMalloc(&dd, (size_t)max_b + 16);
+  if (e == hipSuccess) e = hipMalloc(&doff, 8 * (size_t)(max_n + 1));
+  if (e == hipSuccess) e = hipMalloc(&df, (size_t)max_n + 1);
+  if (e == hipSuccess) e = hipMalloc(&de, 8 * (size_t)max_n + 8);
+  if (e == hipSuccess) e = hipMalloc(&ws, sizeof(unsigned long long) * cus * 64);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e == hipSuccess) e = utf8v::launch_batch_slots_init(ws, cus * 64, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  utf8v_config c;
+  utf8v_get_config(&c);
+  TuneBatch tb;
+  tb.waves_per_cu = c.batch_waves_per_cu;
+  const int64_t t0 = now_ns() + 2000000;
+  for (int64_t i = 0; i < nreq && e == hipSuccess; ++i) {
+    wait_until(t0 + arrival_ns[i]);
+    const int k = pick[i];
+    const int64_t n = req_n[k], o0 = req_offsets[k][0], bytes = req_offsets[k][n] - o0;
+    if (bytes > 0) e = hipMemcpyAsync(dd, req_data[k] + o0, (size_t)bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(doff, req_offsets[k], 8 * (size_t)(n + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && n > 0)
+      e = utf8v::launch_batch(batch_args(dd - o0, doff, n, df, de, ws), tb, cus, st);
+    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(req_flags[k], df, (size_t)n, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(req_errs[k], de, 8 * (size_t)n, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    const int64_t done = now_ns();
+    latency_ns[i] = done - (t0 + arrival_ns[i]);
+    if (span_ns && i == nreq - 1) *span_ns = done - (t0 + arrival_ns[0]);
+  }
+  if (st) (void)hipStreamSynchronize(st);
+  for (void* p : {(void*)dd, (void*)doff, (void*)df, (void*)de, (void*)ws})
+    if (p) (void)hipFree(p);
+  if (st) (void)hipStreamDestroy(st);
+  return e == hipSuccess ? UTF8V_OK : UTF8V_EHIP;
+}
+
+}  // extern "C"

@@ -32,6 +32,10 @@ def test_every_declared_symbol_is_exported_and_bound():
     assert set(_native.SIGNATURES) == set(_declared())
 
 
+def cfg_dict(c):
+    return {f: getattr(c, f) for f, _ in c._fields_}
+
+
 def test_host_only_error_paths():
     lib = _native.load()
     assert lib.utf8v_strerror(0) == b"ok"
@@ -46,6 +50,18 @@ def test_host_only_error_paths():
     assert lib.utf8v_validate_batch_graph(None, None, -2, None, None, None) == _native.UTF8V_EINVAL
     assert lib.utf8v_validate_batch_graph(None, None, 5, None, None, None) == _native.UTF8V_EINVAL
     assert lib.utf8_validate(None, 3) is False
+    # serving: limits are checked before any device call
+    cfg = _native.ServerConfig()
+    assert lib.utf8v_server_default_config(ctypes.byref(cfg)) == 0
+    assert cfg.budget_bytes == 8 << 30 and cfg.max_batch_requests == 4096
+    h = ctypes.c_void_p()
+    small = _native.ServerConfig(**{**cfg_dict(cfg), "budget_bytes": 1 << 20})
+    assert lib.utf8v_server_create(ctypes.byref(small), ctypes.byref(h)) == _native.UTF8V_EINVAL
+    bad = _native.ServerConfig(**{**cfg_dict(cfg), "max_inflight": 0})
+    assert lib.utf8v_server_create(ctypes.byref(bad), ctypes.byref(h)) == _native.UTF8V_EINVAL
+    assert lib.utf8v_server_submit(None, None, None, 0, None, None, None) == _native.UTF8V_EINVAL
+    assert lib.utf8v_server_destroy(None) == _native.UTF8V_EINVAL
+    assert lib.utf8v_clock_ns() > 0
 
 
 def test_config_roundtrip_and_validation():

@@ -1,0 +1,118 @@
+"""CPU tests of the serving loop's planner: the device ring's allocator and the batch layout.
+
+The planner is plain C++ (``csrc/serve_core.hpp``); a small shim built here with
+g++ exposes it.  The allocator is checked against a brute-force occupancy model
+over random reserve / release sequences; the layout against its invariants.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def shim(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("shim") / "libserve_core_shim.so")
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-Wall", "-o", out,
+                           os.path.join(HERE, "serve_core_shim.cpp")])
+    lib = ctypes.CDLL(out)
+    u64, i64, vp = ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p
+    lib.ring_new.restype = vp
+    lib.ring_new.argtypes = [u64]
+    lib.ring_free.argtypes = [vp]
+    lib.ring_reserve.restype = i64
+    lib.ring_reserve.argtypes = [vp, u64]
+    lib.ring_release.argtypes = [vp]
+    lib.ring_used.restype = u64
+    lib.ring_used.argtypes = [vp]
+    lib.ring_capacity.restype = u64
+    lib.ring_capacity.argtypes = [vp]
+    lib.plan.restype = i64
+    lib.plan.argtypes = [i64, vp, vp, vp, u64, vp, vp, vp, vp]
+    return lib
+
+
+def test_ring_never_overlaps_and_is_fifo(shim):
+    rng = np.random.default_rng(1)
+    for trial in range(40):
+        cap = int(rng.choice([4096, 10_000, 65536, 1 << 20]))
+        r = shim.ring_new(cap)
+        capa = shim.ring_capacity(r)
+        assert capa == cap // 256 * 256
+        live = []  # (at, size) in reservation order
+        for step in range(400):
+            if live and (rng.random() < 0.45 or len(live) > 20):
+                shim.ring_release(r)
+                live.pop(0)
+                continue
+            n = int(rng.integers(0, capa // 3 + 2))
+            at = shim.ring_reserve(r, n)
+            size = max(256, -(-max(n, 1) // 256) * 256)
+            if at < 0:
+                # refusal is allowed only when the ring is not empty
+                assert live, (cap, n)
+                continue
+            assert at % 256 == 0 and at + size <= capa
+            for (a, s) in live:
+                assert at + size <= a or a + s <= at, "overlap"
+            live.append((at, size))
+            assert shim.ring_used(r) >= sum(s for _, s in live)
+        while live:
+            shim.ring_release(r)
+            live.pop(0)
+        assert shim.ring_used(r) == 0
+        assert shim.ring_reserve(r, capa) == 0   # an empty ring takes the largest reservation
+        shim.ring_free(r)
+
+
+def test_ring_full_after_wrap(shim):
+    r = shim.ring_new(1024)
+    assert shim.ring_reserve(r, 512) == 0
+    assert shim.ring_reserve(r, 512) == 512
+    shim.ring_release(r)                      # frees [0, 512)
+    assert shim.ring_reserve(r, 512) == 0     # wraps
+    assert shim.ring_reserve(r, 256) == -1    # full: [0,512) and [512,1024) are live
+    shim.ring_release(r)
+    assert shim.ring_reserve(r, 256) == 512
+    shim.ring_free(r)
+
+
+def _plan(shim, bytes_, strings, src, desc=64):
+    k = len(bytes_)
+    b = np.array(bytes_, np.uint64)
+    s = np.array(strings, np.int64)
+    sr = np.array(src, np.uint64)
+    do = np.zeros(k, np.uint64)
+    so = np.zeros(k, np.int64)
+    db = ctypes.c_uint64()
+    reg = np.zeros(6, np.uint64)
+    total_strings = shim.plan(k, b.ctypes.data, s.ctypes.data, sr.ctypes.data, desc, do.ctypes.data,
+                              so.ctypes.data, ctypes.byref(db), reg.ctypes.data)
+    return do.astype(np.int64), so, int(db.value), reg.astype(np.int64), total_strings
+
+
+def test_batch_layout_invariants(shim):
+    rng = np.random.default_rng(2)
+    for trial in range(300):
+        k = int(rng.integers(1, 50))
+        bytes_ = rng.integers(0, 5000, k)
+        strings = rng.integers(0, 40, k)
+        src = rng.integers(0, 1 << 40, k)
+        do, so, db, reg, total = _plan(shim, bytes_, strings, src)
+        # payloads: increasing, disjoint, aligned like their source modulo 16
+        assert ((do % 16) == (src % 16)).all()
+        ends = do + bytes_
+        assert (do[1:] >= ends[:-1]).all() and (do[1:] - ends[:-1] < 16).all()
+        assert db == ends[-1]
+        # strings: each request's strings, then one separator except after the last
+        assert so[0] == 0 and (np.diff(so) == strings[:-1] + 1).all()
+        assert total == so[-1] + strings[-1]
+        desc_at, data_at, off_at, fl_at, er_at, tot = reg
+        assert desc_at == 0 and data_at >= 64 * k
+        assert off_at >= data_at + db + 16 and fl_at >= off_at + 8 * (total + 1)
+        assert er_at >= fl_at + total and tot >= er_at + 8 * total
+        assert all(x % 256 == 0 for x in reg)
