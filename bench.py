@@ -199,14 +199,20 @@ def bench_single(u8, lib, synth, torch, dev, stream, sh, args):
         step()
         torch.cuda.synchronize()
         done += 1
-    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
-            for _ in bufs] for _ in range(args.steps)]
+    # whole-job throughput: K steps back to back, nothing else on the stream
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(evs[k])
+        step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # per-launch durations for the roofline: the same K steps with events around every launch
+    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+            for _ in bufs] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
     if args.copy_probe:
         dst = torch.empty_like(bufs[0])
         for _ in range(3):
@@ -249,7 +255,7 @@ def bench_single(u8, lib, synth, torch, dev, stream, sh, args):
                      "traffic": recorded_traffic() if n == GIB else None,
                      "traffic_unit": "bytes per 1 GiB launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, "
                                      "profiles/single_main_1gib.md)",
-                     "kernel": "single_main (+ single_finalize) per 1 GiB launch, HIP events"},
+                     "kernel": "single_main per 1 GiB launch (one launch per buffer), HIP events"},
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBPS, 1),
         "read_ceiling_GBps": round(read_gbps, 1),
         "pct_of_read_ceiling": round(100 * value / read_gbps, 1),

@@ -24,7 +24,8 @@ constexpr int kParamSlots = 64;
 constexpr int kBatchSlotsPerCu = 64;  // = the largest batch_waves_per_cu  // pinned parameter-block staging slots per stream (graph launches)
 
 struct Workspace {
-  unsigned long long* dmin = nullptr;  // device: first detection position (kNone = none)
+  unsigned long long* dmin = nullptr;  // device: scratch words (result, flag)
+  unsigned long long* state = nullptr; // device: single-buffer state words (idle = kPosNone)
   int64_t* result = nullptr;           // device: first-error offset of the last call
   int* flag = nullptr;                 // device: scratch flag (offset checks)
   int64_t* host = nullptr;             // pinned host copy of result / flag
@@ -76,6 +77,7 @@ void free_workspace(Workspace& w) {
   if (w.dparams) (void)hipFree(w.dparams);
   if (w.hslots) (void)hipHostFree(w.hslots);
   if (w.slot) (void)hipFree(w.slot);
+  if (w.state) (void)hipFree(w.state);
   if (w.dmin) (void)hipFree(w.dmin);
   if (w.host) (void)hipHostFree(w.host);
 }
@@ -96,10 +98,15 @@ int workspace(hipStream_t st, Workspace** out) {
   hipError_t e = hipMalloc(&w->dmin, 64);
   if (e == hipSuccess) e = hipHostMalloc(&w->host, 64, hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc(&w->slot, sizeof(unsigned long long) * slots);
+  if (e == hipSuccess) e = hipMalloc(&w->state, sizeof(unsigned long long) * utf8v::kStateWords);
+  if (e == hipSuccess) {
+    const std::vector<unsigned long long> idle(utf8v::kStateWords, utf8v::kPosNone);
+    e = hipMemcpy(w->state, idle.data(), sizeof(unsigned long long) * idle.size(), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) {
     w->result = reinterpret_cast<int64_t*>(w->dmin) + 1;
     w->flag = reinterpret_cast<int*>(w->dmin + 2);
-    const unsigned long long init[3] = {kNone, 0, 0};
+    const unsigned long long init[3] = {utf8v::kPosNone, 0, 0};
     e = hipMemcpy(w->dmin, init, sizeof init, hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) e = utf8v::launch_batch_slots_init(w->slot, slots, st);
@@ -154,7 +161,7 @@ int enqueue_single(const uint8_t* buf, size_t len, int64_t* dev_out, hipStream_t
   int dev = 0;
   (void)hipGetDevice(&dev);
   const int cus = num_cus_of(dev);
-  hipError_t e = utf8v::launch_single(buf, (uint64_t)len, ws->dmin, dev_out ? dev_out : ws->result, tune_single(),
+  hipError_t e = utf8v::launch_single(buf, (uint64_t)len, ws->state, dev_out ? dev_out : ws->result, tune_single(),
                                       cus > 0 ? cus : 1, st);
   if (e != hipSuccess) return hip_fail(e);
   if (ws_out) *ws_out = ws;

@@ -21,19 +21,13 @@ struct TuneBatch {
   int ascii = 1;
 };
 
-struct SingleArgs {
-  const uint8_t* buf;
-  uint64_t i0, i1;            // interior [i0, i1): 16-byte aligned
-  uint64_t tiles, tiles_per_wave;
-  unsigned long long* dmin;
-};
-
-struct FinalizeArgs {
-  const uint8_t* buf;
-  uint64_t n, i0, i1;
-  unsigned long long* dmin;
-  int64_t* out;
-};
+// State word of a single-buffer call: arrivals << kStateShift | least detection
+// position (kPosNone = none).  Idle (no arrivals, no detection) between calls.
+constexpr int kStateShift = 40;
+constexpr uint64_t kPosNone = (1ull << kStateShift) - 1;
+constexpr int kStateGroups = 64;   // group words under the top word
+constexpr int kStateStride = 32;   // words between state words (256 bytes)
+constexpr int kStateWords = kStateStride * (1 + kStateGroups);
 
 struct BatchArgs {
   const uint8_t* data;
@@ -44,21 +38,7 @@ struct BatchArgs {
   int64_t* first_err;
 };
 
-// Wave minimum of v (kNone = none), then one atomicMin into *dst unless *dst is
-// already lower (on inputs with errors everywhere, most waves then skip the atomic).
-__device__ __forceinline__ void wave_min_to(unsigned long long* dst, uint64_t v, int lane) {
-  if (__any(v != kNone)) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const uint64_t o = __shfl_xor((unsigned long long)v, off);
-      v = o < v ? o : v;
-    }
-    if (lane == 0 && v < __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      atomicMin(dst, (unsigned long long)v);
-  }
-}
-
-hipError_t launch_single(const uint8_t* buf, uint64_t n, unsigned long long* dmin, int64_t* out,
+hipError_t launch_single(const uint8_t* buf, uint64_t n, unsigned long long* state, int64_t* out,
                          const TuneSingle& cfg, int num_cus, hipStream_t st);
 BatchArgs batch_args(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* flags, int64_t* first_err,
                      unsigned long long* slot);

@@ -17,14 +17,28 @@
 //
 // Errors are ORed into a per-lane register (section 6, "error register").  Only
 // when it is non-zero does a lane recompute its chunk to find its first
-// detection position; the wave's minimum then goes to one 64-bit atomicMin.
-// The finalize kernel turns the overall first detection position d into the
-// first-error offset s (the start of the first ill-formed character):
-//   s = max{ k in [max(0, d-3), d] : no character is open at k }.
+// detection position.  Each wave then reports its minimum and its arrival in a
+// 64-bit state word (arrivals in the high bits, least position in the low 40
+// bits), so no memory fence is needed; the last wave to arrive turns the
+// overall first detection position d into the first-error offset s (the start
+// of the first ill-formed character),
+//   s = max{ k in [max(0, d-3), d] : no character is open at k },
+// writes it, and returns the state words to idle for the next call.  The last
+// wave also validates the head and tail chunks outside the interior and
+// applies the end check (section 6.3) before its tiles.
 #include "common.hpp"
 #include "lookup.hpp"
 
 namespace utf8v {
+
+struct SingleArgs {
+  const uint8_t* buf;
+  uint64_t n;                 // buffer length
+  uint64_t i0, i1;            // interior [i0, i1): 16-byte aligned
+  uint64_t tiles, tiles_per_wave;
+  unsigned long long* state;  // top word, then kStateGroups group words kStateStride apart
+  int64_t* out;               // first-error offset, -1 if valid
+};
 
 // Dword of bytes [pos-4, pos), zero below position 0.  (buf + pos) is 16-byte aligned.
 __device__ __forceinline__ uint32_t prev_dword(const uint8_t* __restrict__ buf, uint64_t pos) {
@@ -108,84 +122,149 @@ __device__ __forceinline__ void single_tile(const u32x4 (&x)[U], uint64_t base, 
   }
 }
 
-// One wave takes a contiguous run of tiles; the loads of tile t+1 are issued
-// before tile t is classified, so memory and the VALU work overlap in each wave.
-template <int U, bool ASCII>
-__global__ __launch_bounds__(256) void single_main(SingleArgs a) {
-  const int lane = threadIdx.x & 63;
-  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const uint64_t W = (uint64_t)U * 1024;
-  uint64_t t = wave * a.tiles_per_wave;
-  const uint64_t t_end = t + a.tiles_per_wave < a.tiles ? t + a.tiles_per_wave : a.tiles;
-  if (t >= t_end) return;
-  uint64_t dmin = kNone;
-  int ascii_skip = 0;
-  uint32_t carry = prev_dword(a.buf, a.i0 + t * W);
-  // the buffer's last tile may be partial
-  const uint64_t t_full = (t_end == a.tiles && a.i0 + a.tiles * W > a.i1) ? t_end - 1 : t_end;
-  if (t < t_full) {
-    // two register sets in turn: one is classified while the other's loads are in flight
-    u32x4 xa[U], xb[U];
-    load_tile<U, true>(xa, a.buf, a.i0 + t * W, a.i1, lane);
-    for (; t + 1 < t_full; t += 2) {
-      load_tile<U, true>(xb, a.buf, a.i0 + (t + 1) * W, a.i1, lane);
-      single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii_skip);
-      if (t + 2 < t_full) load_tile<U, true>(xa, a.buf, a.i0 + (t + 2) * W, a.i1, lane);
-      single_tile<U, ASCII, true>(xb, a.i0 + (t + 1) * W, a.i1, lane, carry, dmin, ascii_skip);
-    }
-    if (t < t_full) {
-      single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii_skip);
-      ++t;
+// First detection position in the head chunk [i0-16, i0), the tail chunk
+// [i1, i1+16) and at the end (section 6.3), bytes outside the buffer read as zero;
+// kNone if none.  One thread; every byte load is issued before any use.
+__device__ uint64_t edge_detection(const uint8_t* __restrict__ buf, int64_t n, int64_t i0, int64_t i1) {
+  auto byte_at = [&](int64_t p) -> uint32_t { return (p >= 0 && p < n) ? buf[p] : 0u; };
+  auto dword_at = [&](int64_t p) -> uint32_t {
+    return byte_at(p) | byte_at(p + 1) << 8 | byte_at(p + 2) << 16 | byte_at(p + 3) << 24;
+  };
+  uint32_t h[5], t[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    h[k] = i0 > 0 ? dword_at(i0 - 20 + 4 * k) : 0u;
+    t[k] = i1 < n ? dword_at(i1 - 4 + 4 * k) : 0u;
+  }
+  const uint32_t last = dword_at(n - 4);
+  uint64_t d = kNone;
+  for (int j = 0; j < 4 && i0 > 0; ++j) {
+    const uint32_t e = position_errors(h[j + 1], h[j]);
+    if (e) {
+      const int64_t p = i0 - 16 + 4 * j + first_byte(e);
+      if (p >= 0) d = (uint64_t)p;
+      break;
     }
   }
-  if (t < t_end) {
-    u32x4 x[U];
-    load_tile<U, false>(x, a.buf, a.i0 + t * W, a.i1, lane);
-    single_tile<U, ASCII, false>(x, a.i0 + t * W, a.i1, lane, carry, dmin, ascii_skip);
+  for (int j = 0; j < 4 && i1 < n && d == kNone; ++j) {
+    const uint32_t e = position_errors(t[j + 1], t[j]);
+    if (e) {
+      d = (uint64_t)(i1 + 4 * j + first_byte(e));
+      break;
+    }
   }
-  wave_min_to(a.dmin, dmin, lane);
+  if (n > 0 && open_at_end(last) && (uint64_t)n < d) d = (uint64_t)n;
+  return d;
 }
 
-// Head and tail chunks, the end check (section 6.3), and d -> s.
-__global__ void single_finalize(FinalizeArgs a) {
-  if (threadIdx.x != 0) return;
-  const uint8_t* buf = a.buf;
-  const int64_t n = (int64_t)a.n;
-  uint64_t d = *a.dmin;
-  auto byte_at = [&](int64_t p) -> uint32_t { return (p >= 0 && p < n) ? buf[p] : 0u; };
-  auto chunk = [&](int64_t c) {
-    uint32_t w[5];
-    for (int k = 0; k < 5; ++k) {
-      uint32_t v = 0;
-      for (int b = 0; b < 4; ++b) v |= byte_at(c - 4 + 4 * k + b) << (8 * b);
-      w[k] = v;
+// First detection d -> first-error offset s: the latest k in [d-3, d] at which no
+// character is open (bytes outside the buffer read as zero).
+__device__ int64_t resolve_first_error(const uint8_t* __restrict__ buf, int64_t n, int64_t d) {
+  uint32_t w[7];  // w[i] = byte d-i
+#pragma unroll
+  for (int i = 1; i <= 6; ++i) w[i] = (d - i >= 0 && d - i < n) ? buf[d - i] : 0u;
+#pragma unroll
+  for (int i = 0; i <= 3; ++i)
+    if (d - i >= 0 && w[i + 1] < 0xC0 && w[i + 2] < 0xE0 && w[i + 3] < 0xF0) return d - i;
+  return d;
+}
+
+// One arrival on a state word carrying `mine` (kPosNone = no detection): the
+// arrival count goes up by one and the position becomes the least of both.  An
+// arrival that does not lower the position is a plain atomic add; otherwise a
+// compare-and-swap loop, left as soon as the word's position is no longer higher.
+// Returns the word before this arrival.
+__device__ __forceinline__ uint64_t arrive(unsigned long long* w, uint64_t mine) {
+  if (mine != kPosNone) {
+    uint64_t old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while ((old & kPosNone) > mine) {
+      const uint64_t nw = (old & ~kPosNone) + (1ull << kStateShift) + mine;
+      const uint64_t seen = atomicCAS(w, (unsigned long long)old, (unsigned long long)nw);
+      if (seen == old) return old;
+      old = seen;
     }
-    for (int j = 0; j < 4; ++j) {
-      const uint32_t e = position_errors(w[j + 1], w[j]);
-      if (e) {
-        const int64_t p = c + 4 * j + first_byte(e);
-        if (p >= 0 && (uint64_t)p < d) d = (uint64_t)p;
-        break;
+  }
+  return atomicAdd(w, 1ull << kStateShift);
+}
+
+// One wave takes a contiguous run of tiles; the loads of tile t+1 are issued
+// before tile t is classified, so memory and the VALU work overlap in each wave.
+// Each workgroup then reports once, by whichever of its waves finishes last (the
+// others exit without waiting): on one of up to kStateGroups group words
+// (workgroup index modulo the group count), and the last workgroup of a group
+// reports the group on the top word, so no word sees many arrivals.
+template <int U, bool ASCII>
+__global__ __launch_bounds__(256) void single_main(SingleArgs a) {
+  __shared__ unsigned long long blk_min;  // least detection of the workgroup's waves so far
+  __shared__ unsigned blk_done;           // waves of the workgroup that have finished
+  const int lane = threadIdx.x & 63;
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  const uint64_t W = (uint64_t)U * 1024;
+  if (threadIdx.x == 0) {
+    blk_min = kPosNone;
+    blk_done = 0;
+  }
+  __syncthreads();
+  uint64_t edge = kNone;  // the last wave (usually the one with the fewest tiles) also checks the edges
+  if (wave == waves - 1 && lane == 0) edge = edge_detection(a.buf, (int64_t)a.n, (int64_t)a.i0, (int64_t)a.i1);
+  uint64_t t = wave * a.tiles_per_wave;
+  const uint64_t t_end = t + a.tiles_per_wave < a.tiles ? t + a.tiles_per_wave : a.tiles;
+  uint64_t dmin = kNone;
+  if (t < t_end) {
+    int ascii_skip = 0;
+    uint32_t carry = prev_dword(a.buf, a.i0 + t * W);
+    // the buffer's last tile may be partial
+    const uint64_t t_full = (t_end == a.tiles && a.i0 + a.tiles * W > a.i1) ? t_end - 1 : t_end;
+    if (t < t_full) {
+      // two register sets in turn: one is classified while the other's loads are in flight
+      u32x4 xa[U], xb[U];
+      load_tile<U, true>(xa, a.buf, a.i0 + t * W, a.i1, lane);
+      for (; t + 1 < t_full; t += 2) {
+        load_tile<U, true>(xb, a.buf, a.i0 + (t + 1) * W, a.i1, lane);
+        single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii_skip);
+        if (t + 2 < t_full) load_tile<U, true>(xa, a.buf, a.i0 + (t + 2) * W, a.i1, lane);
+        single_tile<U, ASCII, true>(xb, a.i0 + (t + 1) * W, a.i1, lane, carry, dmin, ascii_skip);
+      }
+      if (t < t_full) {
+        single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii_skip);
+        ++t;
       }
     }
-  };
-  if (a.i0 > 0) chunk((int64_t)a.i0 - 16);
-  if ((int64_t)a.i1 < n) chunk((int64_t)a.i1);
-  if (n > 0) {
-    uint32_t p = 0;
-    for (int b = 0; b < 4; ++b) p |= byte_at(n - 4 + b) << (8 * b);
-    if (open_at_end(p) && (uint64_t)n < d) d = (uint64_t)n;
-  }
-  int64_t s = -1;
-  if (d != kNone) {
-    const int64_t dd = (int64_t)d;
-    s = dd;  // unreachable fallback: one of the four candidates always closes
-    for (int64_t k = dd; k >= 0 && k >= dd - 3; --k) {
-      if (byte_at(k - 1) < 0xC0 && byte_at(k - 2) < 0xE0 && byte_at(k - 3) < 0xF0) { s = k; break; }
+    if (t < t_end) {
+      u32x4 x[U];
+      load_tile<U, false>(x, a.buf, a.i0 + t * W, a.i1, lane);
+      single_tile<U, ASCII, false>(x, a.i0 + t * W, a.i1, lane, carry, dmin, ascii_skip);
     }
   }
-  *a.out = s;
-  *a.dmin = kNone;
+  dmin = edge < dmin ? edge : dmin;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor((unsigned long long)dmin, off);
+    dmin = o < dmin ? o : dmin;
+  }
+  if (lane != 0) return;
+  // the workgroup's last wave to finish reports for all of them (no barrier: the others exit)
+  atomicMin(&blk_min, (unsigned long long)(dmin < kPosNone ? dmin : kPosNone));
+  const unsigned before = __hip_atomic_fetch_add(&blk_done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if (before != (blockDim.x >> 6) - 1) return;
+  const uint64_t mine = __hip_atomic_load(&blk_min, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const uint64_t blocks = gridDim.x;
+  const uint64_t groups = blocks < (uint64_t)kStateGroups ? blocks : (uint64_t)kStateGroups;
+  const uint64_t g = blockIdx.x % groups;
+  const uint64_t gsize = blocks / groups + (g < blocks % groups ? 1 : 0);
+  unsigned long long* gw = a.state + (size_t)kStateStride * (1 + g);
+  const uint64_t old = arrive(gw, mine);
+  if ((old >> kStateShift) != gsize - 1) return;
+  // last workgroup of its group: the group's position goes to the top word
+  const uint64_t gpos = (old & kPosNone) < mine ? (old & kPosNone) : mine;
+  atomicExch(gw, (unsigned long long)kPosNone);
+  const uint64_t top = arrive(a.state, gpos);
+  if ((top >> kStateShift) != groups - 1) return;
+  // last group: every workgroup has reported
+  const uint64_t pos = (top & kPosNone) < gpos ? (top & kPosNone) : gpos;
+  *a.out = pos == kPosNone ? -1 : resolve_first_error(a.buf, (int64_t)a.n, (int64_t)pos);
+  atomicExch(a.state, (unsigned long long)kPosNone);
 }
 
 // ---- launch -----------------------------------------------------------------------------
@@ -196,37 +275,30 @@ static hipError_t launch_single_t(const SingleArgs& a, int grid, hipStream_t st)
   return hipGetLastError();
 }
 
-hipError_t launch_single(const uint8_t* buf, uint64_t n, unsigned long long* dmin, int64_t* out,
+hipError_t launch_single(const uint8_t* buf, uint64_t n, unsigned long long* state, int64_t* out,
                          const TuneSingle& cfg, int num_cus, hipStream_t st) {
+  if (n >= kPosNone) return hipErrorInvalidValue;
   const uint64_t mis = (uint64_t)(reinterpret_cast<uintptr_t>(buf) & 15);
   const uint64_t i0 = mis ? 16 - mis : 0;
   uint64_t i1 = i0;
   if (n > i0) i1 = i0 + ((n - i0) & ~uint64_t(15));
-  if (i1 > i0) {
-    const int U = cfg.unroll;
-    const uint64_t W = (uint64_t)U * 1024;
-    SingleArgs a;
-    a.buf = buf; a.i0 = i0; a.i1 = i1; a.dmin = dmin;
-    a.tiles = (i1 - i0 + W - 1) / W;
-    const uint64_t max_waves = (uint64_t)num_cus * (uint64_t)cfg.waves_per_cu;
-    a.tiles_per_wave = (a.tiles + max_waves - 1) / max_waves;
-    if (a.tiles_per_wave < (uint64_t)cfg.min_tiles_per_wave) a.tiles_per_wave = cfg.min_tiles_per_wave;
-    const uint64_t waves = (a.tiles + a.tiles_per_wave - 1) / a.tiles_per_wave;
-    const int grid = (int)((waves + 3) / 4);
-    hipError_t e;
-    const bool asc = cfg.ascii != 0;
-    switch (U) {
-      case 1: e = asc ? launch_single_t<1, true>(a, grid, st) : launch_single_t<1, false>(a, grid, st); break;
-      case 2: e = asc ? launch_single_t<2, true>(a, grid, st) : launch_single_t<2, false>(a, grid, st); break;
-      case 8: e = asc ? launch_single_t<8, true>(a, grid, st) : launch_single_t<8, false>(a, grid, st); break;
-      default: e = asc ? launch_single_t<4, true>(a, grid, st) : launch_single_t<4, false>(a, grid, st); break;
-    }
-    if (e != hipSuccess) return e;
+  const int U = cfg.unroll;
+  const uint64_t W = (uint64_t)U * 1024;
+  SingleArgs a;
+  a.buf = buf; a.n = n; a.i0 = i0; a.i1 = i1; a.state = state; a.out = out;
+  a.tiles = i1 > i0 ? (i1 - i0 + W - 1) / W : 0;
+  const uint64_t max_waves = (uint64_t)num_cus * (uint64_t)cfg.waves_per_cu;
+  a.tiles_per_wave = (a.tiles + max_waves - 1) / max_waves;
+  if (a.tiles_per_wave < (uint64_t)cfg.min_tiles_per_wave) a.tiles_per_wave = cfg.min_tiles_per_wave;
+  const uint64_t waves = a.tiles ? (a.tiles + a.tiles_per_wave - 1) / a.tiles_per_wave : 1;
+  const int grid = (int)((waves + 3) / 4);  // at least one workgroup: it also does the edges and the result
+  const bool asc = cfg.ascii != 0;
+  switch (U) {
+    case 1: return asc ? launch_single_t<1, true>(a, grid, st) : launch_single_t<1, false>(a, grid, st);
+    case 2: return asc ? launch_single_t<2, true>(a, grid, st) : launch_single_t<2, false>(a, grid, st);
+    case 8: return asc ? launch_single_t<8, true>(a, grid, st) : launch_single_t<8, false>(a, grid, st);
+    default: return asc ? launch_single_t<4, true>(a, grid, st) : launch_single_t<4, false>(a, grid, st);
   }
-  FinalizeArgs f;
-  f.buf = buf; f.n = n; f.i0 = i0; f.i1 = i1; f.dmin = dmin; f.out = out;
-  hipLaunchKernelGGL(single_finalize, dim3(1), dim3(64), 0, st, f);
-  return hipGetLastError();
 }
 
 }  // namespace utf8v
