@@ -62,6 +62,7 @@ def parse():
     ap.add_argument("--no-tail-copies", action="store_true", help="skip the copies with a tail error")
     ap.add_argument("--config", default="", help="launch overrides, e.g. unroll=4,waves_per_cu=24,ascii=1")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop part")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph / small-batch launch comparison")
     ap.add_argument("--serve-loads", default="10000,50000,200000", help="offered loads, requests/s")
     ap.add_argument("--serve-requests", type=int, default=100_000, help="measured requests per load")
     ap.add_argument("--serve-baseline-requests", type=int, default=20_000,
@@ -329,7 +330,8 @@ def bench_batch(u8, lib, synth, torch, dev, stream, sh, args):
         per_string = sub / (time.perf_counter() - t0)
         if not np.array_equal(outs.cpu().numpy(), expected[:sub]):
             raise SystemExit("wrong per-string result")
-    graph = bench_graph(u8, lib, torch, td, to, flags, ferr, nstr, offsets, expected, stream, sh, reps, warm)
+    graph = None if args.no_graph else bench_graph(u8, lib, torch, td, to, flags, ferr, nstr, offsets, expected,
+                                                   stream, sh, reps, warm)
     payload = int(offsets[-1] - offsets[0])
     algo = payload + 17 * nstr   # payload + offsets (8 B) + flag (1 B) + first_err (8 B) per string
     return {"workload": "1,000,000 strings, log-normal lengths (median 64 B, sigma 1.2, 1 B..64 KiB), "
