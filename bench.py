@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--config", default="", help="launch overrides, e.g. unroll=4,waves_per_cu=24,ascii=1")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop part")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph / small-batch launch comparison")
+    ap.add_argument("--no-heavy", action="store_true", help="skip the heavy-tail batches")
     ap.add_argument("--serve-loads", default="10000,50000,200000", help="offered loads, requests/s")
     ap.add_argument("--serve-requests", type=int, default=100_000, help="measured requests per load")
     ap.add_argument("--serve-baseline-requests", type=int, default=20_000,
@@ -100,6 +101,10 @@ def main():
     # ---- batched: 1M log-normal strings vs one launch per string ------------------------------
     if not args.no_batch:
         result["batched"] = bench_batch(u8, lib, synth, torch, dev, stream, sh, args)
+
+    # ---- heavy-tail batches: 20,000 Pareto strings, ~125 MiB and ~4 GiB ------------------------
+    if not args.no_batch and not args.no_heavy:
+        result["batched_heavy_tail"] = bench_heavy(u8, lib, synth, torch, dev, stream, sh, args)
 
     # ---- serving: continuous batching under Poisson load vs one launch per request -----------
     if not args.no_serve:
@@ -391,6 +396,53 @@ def bench_graph(u8, lib, torch, td, to, flags, ferr, nstr, offsets, expected, st
                 raise SystemExit(f"wrong {name} small-batch result")
         out[f"n{n}"] = row
     return out
+
+
+def bench_heavy(u8, lib, synth, torch, dev, stream, sh, args):
+    """20,000 strings, Pareto lengths (alpha 1.1, clipped at 64 MiB), per-string valid variant, 0.5% errors.
+
+    x_m = 1 KiB gives ~125 MiB in total; x_m = 34 KiB gives ~4 GiB.  Timed through
+    the direct launch and the captured-graph entry point.
+    """
+    rows = []
+    for name, xm in (("xm_1KiB", 1024.0), ("xm_34KiB", 34 * 1024.0)):
+        t0 = time.time()
+        data, offsets, expected = synth.pareto_batch(20_000, 3, xm=xm)
+        td = torch.from_numpy(data).to(dev)
+        to = torch.from_numpy(offsets).to(dev)
+        del data
+        n = offsets.size - 1
+        flags = torch.empty(n, dtype=torch.uint8, device=dev)
+        ferr = torch.empty(n, dtype=torch.int64, device=dev)
+        log(f"heavy-tail {name}: {int(offsets[-1]) / 2**20:.0f} MiB ready in {time.time() - t0:.1f}s")
+        row = {"workload": name, "payload_bytes": int(offsets[-1] - offsets[0]),
+               "largest_string": int(np.diff(offsets).max())}
+        for mode, fn in (("direct", lib.utf8v_validate_batch_async), ("graph", lib.utf8v_validate_batch_graph)):
+            def run():
+                rc = fn(td.data_ptr(), to.data_ptr(), n, flags.data_ptr(), ferr.data_ptr(), sh)
+                if rc:
+                    raise u8.Utf8vError(rc, mode)
+            ferr.fill_(-7)
+            t_w = time.perf_counter()
+            while time.perf_counter() - t_w < args.warmup_seconds:
+                run()
+                torch.cuda.synchronize()
+            if not np.array_equal(ferr.cpu().numpy(), expected):
+                raise SystemExit(f"wrong heavy-tail result ({name}, {mode})")
+            reps = max(5, args.steps // 2)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                run()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) * 1e-3 / reps
+            row[mode] = {"ms": round(t * 1e3, 3), "payload_GBps": round(row["payload_bytes"] / t / 1e9, 1),
+                         "strings_per_s": round(n / t)}
+        rows.append(row)
+        del td, to, flags, ferr
+        torch.cuda.empty_cache()
+    return rows
 
 
 def bench_serving(synth, args):

@@ -196,23 +196,29 @@ constexpr uint64_t kSlotNone = (1ull << kSlotShift) - 1;
 
 // String k runs across waves ws < we; this wave contributes the first detection d it
 // saw in its part (kNoneRel if none).  The last contributor writes the result and
-// empties the slot.  Lane 0.
+// empties the slot.  Lane 0.  A contribution that does not lower the slot's
+// detection (the usual case: none) is a plain atomic add of one arrival, so the
+// many waves inside one long string do not contend in compare-and-swap loops.
 __device__ void cross_wave(const BatchArgs& a, int64_t k, int64_t st, int64_t en, int64_t d, int64_t c0,
                            int64_t per) {
   const int64_t ws = wave_of(st, c0, per), we = wave_of(en, c0, per);
   unsigned long long* slot = a.slot + ws;
   const uint64_t mine = d == kNoneRel ? kSlotNone : (uint64_t)d;
-  uint64_t old = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  uint64_t arrived, best;
-  for (;;) {  // lock-free: a failed exchange means another wave's succeeded
-    arrived = (old >> kSlotShift) + 1;
-    const uint64_t prev = old & kSlotNone;
-    best = prev < mine ? prev : mine;
-    const uint64_t seen = atomicCAS(slot, (unsigned long long)old, (unsigned long long)((arrived << kSlotShift) | best));
-    if (seen == old) break;
-    old = seen;
+  uint64_t old = 0;
+  bool done = false;
+  if (mine != kSlotNone) {
+    old = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while ((old & kSlotNone) > mine) {
+      const uint64_t nw = (old & ~kSlotNone) + (1ull << kSlotShift) + mine;
+      const uint64_t seen = atomicCAS(slot, (unsigned long long)old, (unsigned long long)nw);
+      if (seen == old) { done = true; break; }
+      old = seen;
+    }
   }
-  if ((int64_t)arrived == we - ws + 1) {
+  if (!done) old = atomicAdd(slot, 1ull << kSlotShift);
+  if ((int64_t)(old >> kSlotShift) + 1 == we - ws + 1) {
+    const uint64_t prev = old & kSlotNone;
+    const uint64_t best = prev < mine ? prev : mine;
     atomicExch(slot, (unsigned long long)kSlotNone);
     write_result(a, k, a.data + st, en - st, best == kSlotNone ? kNoneRel : (int64_t)best);
   }
