@@ -64,6 +64,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop part")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph / small-batch launch comparison")
     ap.add_argument("--no-heavy", action="store_true", help="skip the heavy-tail batches")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--serve-loads", default="10000,50000,200000", help="offered loads, requests/s")
     ap.add_argument("--serve-requests", type=int, default=100_000, help="measured requests per load")
     ap.add_argument("--serve-baseline-requests", type=int, default=20_000,
@@ -88,6 +89,7 @@ def main():
     lib = u8.load()
     if args.config:
         u8.set_config(**{k: int(v) for k, v in (kv.split("=") for kv in args.config.split(","))})
+        args.no_autotune = True
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream or None
@@ -165,6 +167,8 @@ def bench_single(u8, lib, synth, torch, dev, stream, sh, args):
             raise SystemExit(f"wrong result on {name}: {got} != {e}")
         if e is None and name != "random" and got != -1:
             raise SystemExit(f"wrong result on {name}: {got} != -1")
+
+    tuned = None if args.no_autotune else autotune_single(u8, lib, bufs[:len(chosen)])
 
     out = torch.empty(len(bufs), dtype=torch.int64, device=dev)
     ptrs = [t.data_ptr() for t in bufs]
@@ -267,9 +271,50 @@ def bench_single(u8, lib, synth, torch, dev, stream, sh, args):
         "pct_of_read_ceiling": round(100 * value / read_gbps, 1),
         "per_variant_GBps": per_variant,
         "GiBps": round(total_bytes / wall / GIB, 1),
+        "autotune": tuned,
     }
 
     return result, host
+
+
+def _top(cands, ms, k=4):
+    order = np.argsort(ms)[:k]
+    return [{"config": cands[i], "ms": round(float(ms[i]), 4)} for i in order]
+
+
+def autotune_single(u8, lib, bufs, rounds=7):
+    """The native autotuner on the benchmark's own 1 GiB buffers (one of each variant)."""
+    import ctypes
+    P = ctypes.c_void_p * len(bufs)
+    S = ctypes.c_size_t * len(bufs)
+    best = u8.Config()
+    times = (ctypes.c_float * 64)()
+    t0 = time.time()
+    k = lib.utf8v_autotune_single(P(*[b.data_ptr() for b in bufs]), S(*[b.numel() for b in bufs]), len(bufs),
+                                  rounds, ctypes.byref(best), times, 64)
+    if k < 0:
+        raise u8.Utf8vError(k, "utf8v_autotune_single")
+    cands = [f"unroll={u},waves_per_cu={w},ascii={a}" for u in (2, 4, 8) for w in (8, 12, 16, 20, 24, 32, 40)
+             for a in (0, 1)]
+    ms = np.array([times[i] for i in range(k)])
+    log(f"autotuned single-buffer launch in {time.time() - t0:.1f}s: {best.as_dict()}")
+    return {"chosen": {f: best.as_dict()[f] for f in ("unroll", "waves_per_cu", "ascii")}, "rounds": rounds,
+            "fastest_ms_for_all_buffers": _top(cands, ms)}
+
+
+def autotune_batch(u8, lib, td, to, n, flags, ferr, rounds=7):
+    import ctypes
+    best = u8.Config()
+    times = (ctypes.c_float * 64)()
+    k = lib.utf8v_autotune_batch(td.data_ptr(), to.data_ptr(), n, flags.data_ptr(), ferr.data_ptr(), rounds,
+                                 ctypes.byref(best), times, 64)
+    if k < 0:
+        raise u8.Utf8vError(k, "utf8v_autotune_batch")
+    cands = [f"batch_waves_per_cu={w}" for w in (4, 8, 12, 16, 20, 24, 32, 48, 64)]
+    ms = np.array([times[i] for i in range(k)])
+    log(f"autotuned batch launch: {best.as_dict()}")
+    return {"chosen": {"batch_waves_per_cu": best.batch_waves_per_cu}, "rounds": rounds,
+            "fastest_ms_x3": _top(cands, ms)}
 
 
 def bench_batch(u8, lib, synth, torch, dev, stream, sh, args):
@@ -282,6 +327,7 @@ def bench_batch(u8, lib, synth, torch, dev, stream, sh, args):
     log(f"batch inputs ready in {time.time() - t0:.1f}s: {data.size} bytes")
     fn = lib.utf8v_validate_batch_async
     nstr = args.batch_strings
+    tuned = None if args.no_autotune else autotune_batch(u8, lib, td, to, nstr, flags, ferr)
 
     def run():
         rc = fn(td.data_ptr(), to.data_ptr(), nstr, flags.data_ptr(), ferr.data_ptr(), sh)
@@ -347,7 +393,7 @@ def bench_batch(u8, lib, synth, torch, dev, stream, sh, args):
             "algorithmic_GBps_warm": round(algo / warm / 1e9, 1),
             "per_string_launch_strings_per_s": round(per_string) if per_string else None,
             "speedup_vs_per_string_launch": round(nstr / warm / per_string, 1) if per_string else None,
-            "graph": graph}
+            "graph": graph, "autotune": tuned, "launch": {"batch_waves_per_cu": u8.get_config()["batch_waves_per_cu"]}}
 
 
 def bench_graph(u8, lib, torch, td, to, flags, ferr, nstr, offsets, expected, stream, sh, reps, warm):

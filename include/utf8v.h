@@ -191,7 +191,7 @@ int utf8v_serve_replay(const utf8v_server_config *cfg, int mode, const uint8_t *
                        int64_t *const *req_errs, int npool, const int64_t *arrival_ns, const int32_t *pick,
                        int64_t nreq, int64_t *latency_ns, int64_t *span_ns);
 
-/* ---- tuning (see utf8v_tune_* in the Python package for the autotuner) ------------ */
+/* ---- tuning ------------------------------------------------------------------------- */
 
 typedef struct {
   int32_t unroll;            /* single buffer: dwordx4 loads per lane per tile, 1, 2, 4 or 8 */
@@ -204,6 +204,27 @@ typedef struct {
 /* Read / replace the launch configuration of the calling process (all devices). */
 int utf8v_get_config(utf8v_config *cfg);
 int utf8v_set_config(const utf8v_config *cfg);
+
+/*
+ * utf8v_autotune_single -- time every single-buffer launch configuration
+ * (unroll 2/4/8 x waves per CU 8..40 x ASCII skip off/on) on the sample buffers
+ * bufs[i][0..lens[i]) (device memory; bufs and lens are host arrays of nbufs),
+ * in `rounds` interleaved rounds, and keep the one with the least median time:
+ * it becomes the process configuration and is stored in *best.  times_ms (host,
+ * may be NULL) receives up to max_times per-candidate medians in candidate order.
+ * Returns the number of candidates, or a negative status (configuration unchanged).
+ * Results never depend on the configuration; only speed does.
+ */
+int utf8v_autotune_single(const uint8_t *const *bufs, const size_t *lens, int nbufs, int rounds,
+                          utf8v_config *best, float *times_ms, int max_times);
+
+/*
+ * utf8v_autotune_batch -- the same for the batch kernel's persistent grid
+ * (4..64 one-wave workgroups per CU) on a sample CSR batch (device memory, with
+ * output arrays of n entries the timing runs overwrite).
+ */
+int utf8v_autotune_batch(const uint8_t *data, const int64_t *offsets, int64_t n, uint8_t *out_flags,
+                         int64_t *out_first_err, int rounds, utf8v_config *best, float *times_ms, int max_times);
 
 /* ---- diagnostics and measurement -------------------------------------------------- */
 

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libutf8v.so")
 BUILD = os.path.join(PKG, "_build")
-SOURCES = ["single.hip", "batch.hip", "misc.hip", "serve.hip", "api.hip"]
+SOURCES = ["single.hip", "batch.hip", "misc.hip", "serve.hip", "tune.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          # no packed-FP32 instructions anywhere in device code

@@ -341,6 +341,30 @@ def test_tuning_invariance(u8):
         u8.set_config(**old)
 
 
+def test_autotune_keeps_results_exact(u8, tmp_path):
+    """The autotuner picks and applies a configuration; results stay bit-exact; the cache applies it."""
+    from paper_2010_03090_amd import tune
+    old = u8.get_config()
+    b = synth.text(3_000_001, "mixed", 19)
+    synth.inject(b, 2_500_000, "too_large", 2)
+    exp = oracle.first_error(b)
+    data, offsets, _ = synth.lognormal_batch(30_000, 20)
+    f_o, e_o = oracle.first_error_batch(data, offsets)
+    path = str(tmp_path / "tune.json")
+    try:
+        say("case: autotune")
+        cfg = tune.autotune(sample_mib=16, batch_strings=20_000, rounds=2, path=path)
+        assert u8.get_config() == cfg
+        assert u8.first_error(dev(b)) == exp
+        flags, ferr = u8.validate_batch(dev(data), dev(offsets))
+        torch.cuda.synchronize()
+        assert np.array_equal(ferr.cpu().numpy(), e_o) and np.array_equal(flags.cpu().numpy(), f_o)
+        u8.set_config(**old)
+        assert tune.apply_cached(path) == cfg and u8.get_config() == cfg
+    finally:
+        u8.set_config(**old)
+
+
 def test_async_and_streams(u8):
     b = synth.text(1 << 20, "cjk", 9)
     synth.inject(b, 777_777, 4, 1)
