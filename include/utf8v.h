@@ -104,6 +104,46 @@ int utf8v_validate_batch_async(const uint8_t *data, const int64_t *offsets, int6
 int utf8v_validate_batch_graph(const uint8_t *data, const int64_t *offsets, int64_t n,
                                uint8_t *out_flags, int64_t *out_first_err, void *stream);
 
+/* ---- streams: one byte sequence fed in chunks --------------------------------------- */
+
+/*
+ * A stream validates the concatenation of the chunks fed to it, as one buffer
+ * (section 6: the previous input carries over; section 6.3: the end check is
+ * applied once, at finish).  Splitting the bytes anywhere -- inside a
+ * character, into empty or one-byte chunks -- gives the same result as
+ * validating them whole.  The state (first-error offset and the last 8 bytes)
+ * lives on the device, so updates are asynchronous and ordered by the HIP
+ * stream they are enqueued on; use one HIP stream per utf8v_stream.
+ */
+typedef struct utf8v_stream utf8v_stream;
+
+/* Create an empty stream on the current device (its reset is enqueued on `stream`). */
+int utf8v_stream_create(utf8v_stream **out, void *stream);
+
+/*
+ * Enqueue the validation of the next chunk (device memory, len bytes; may be
+ * NULL iff len == 0).  The chunk must stay unchanged until the call is done on
+ * `stream`.  Offsets reported later are stream positions.
+ */
+int utf8v_stream_update(utf8v_stream *s, const uint8_t *chunk, size_t len, void *stream);
+
+/*
+ * Apply the end check, wait, and report: *first_err (host, may be NULL) = the
+ * stream's first-error offset (start of the first ill-formed character), or -1.
+ * Returns 1 if valid, 0 if invalid, or a negative status.  The stream may be fed
+ * further afterwards (a later finish checks the longer stream's end).
+ */
+int utf8v_stream_finish(utf8v_stream *s, int64_t *first_err, void *stream);
+
+/* Enqueue a reset to the empty stream. */
+int utf8v_stream_reset(utf8v_stream *s, void *stream);
+
+/* Bytes fed since creation or the last reset (host-side count), -1 for NULL. */
+int64_t utf8v_stream_position(const utf8v_stream *s);
+
+/* Free the stream.  No call on it may be in flight. */
+int utf8v_stream_destroy(utf8v_stream *s);
+
 /*
  * utf8v_check_offsets -- 1 if offsets[0..n] (device memory) is non-decreasing
  * with offsets[0] >= 0, else 0; negative status on error.  Synchronous.

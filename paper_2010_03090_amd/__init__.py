@@ -17,7 +17,7 @@ from . import _native
 from ._native import Config, Utf8vError, check, load
 
 __all__ = ["validate", "first_error", "validate_async", "validate_batch", "validate_batch_async",
-           "validate_batch_graph",
+           "validate_batch_graph", "Stream",
            "classify", "check_offsets", "get_config", "set_config", "num_cus", "read_ceiling", "copy",
            "Config", "Utf8vError", "load"]
 
@@ -106,6 +106,55 @@ def validate_batch(data, offsets, stream=None):
     ferr = torch.empty(max(n, 0), dtype=torch.int64, device=offsets.device)
     validate_batch_async(data, offsets, flags, ferr, stream)
     return flags, ferr
+
+
+class Stream:
+    """Validate one byte sequence fed in chunks (CUDA uint8 tensors); any split gives the whole's result.
+
+    Keep each chunk alive until the next finish() (or synchronize the stream).
+    """
+
+    def __init__(self, stream=None):
+        self._stream = stream
+        h = ctypes.c_void_p()
+        check(load().utf8v_stream_create(ctypes.byref(h), _stream_handle(stream)), "utf8v_stream_create")
+        self._h = h
+        self._keep = []
+
+    def update(self, chunk) -> None:
+        _dev_u8(chunk, "chunk")
+        if chunk.numel() == 0:
+            return
+        check(load().utf8v_stream_update(self._h, chunk.data_ptr(), chunk.numel(), _stream_handle(self._stream)),
+              "utf8v_stream_update")
+        self._keep.append(chunk)
+
+    def finish(self) -> int:
+        """First-error offset of everything fed so far (-1 if valid); waits for the stream."""
+        out = ctypes.c_int64(0)
+        check(load().utf8v_stream_finish(self._h, ctypes.byref(out), _stream_handle(self._stream)),
+              "utf8v_stream_finish")
+        self._keep.clear()
+        return int(out.value)
+
+    @property
+    def position(self) -> int:
+        return int(load().utf8v_stream_position(self._h))
+
+    def reset(self) -> None:
+        check(load().utf8v_stream_reset(self._h, _stream_handle(self._stream)), "utf8v_stream_reset")
+
+    def close(self) -> None:
+        if self._h:
+            _torch().cuda.current_stream().synchronize() if self._stream is None else self._stream.synchronize()
+            check(load().utf8v_stream_destroy(self._h), "utf8v_stream_destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def check_offsets(offsets, stream=None) -> bool:

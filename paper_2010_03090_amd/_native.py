@@ -68,6 +68,12 @@ SIGNATURES = {
     "utf8v_server_stats": (_i32, [_vp, _vp]),
     "utf8v_server_destroy": (_i32, [_vp]),
     "utf8v_clock_ns": (_i64, []),
+    "utf8v_stream_create": (_i32, [ctypes.POINTER(_vp), _vp]),
+    "utf8v_stream_update": (_i32, [_vp, _vp, _sz, _vp]),
+    "utf8v_stream_finish": (_i32, [_vp, ctypes.POINTER(_i64), _vp]),
+    "utf8v_stream_reset": (_i32, [_vp, _vp]),
+    "utf8v_stream_position": (_i64, [_vp]),
+    "utf8v_stream_destroy": (_i32, [_vp]),
     "utf8v_autotune_single": (_i32, [_vp, _vp, _i32, _i32, ctypes.POINTER(Config), _vp, _i32]),
     "utf8v_autotune_batch": (_i32, [_vp, _vp, _i64, _vp, _vp, _i32, ctypes.POINTER(Config), _vp, _i32]),
     "utf8v_serve_replay": (_i32, [_pcfg, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _i64, _vp, _vp]),

@@ -281,6 +281,90 @@ int utf8v_validate_batch_graph(const uint8_t* data, const int64_t* offsets, int6
   return set_status(UTF8V_OK);
 }
 
+struct utf8v_stream {
+  int dev = 0;
+  int64_t* dstate = nullptr;  // device: {first-error offset of the chunks, history (8 bytes), end-check result}
+  int64_t* host = nullptr;    // pinned copy of dstate
+  int64_t total = 0;          // bytes fed so far
+};
+
+int utf8v_stream_create(utf8v_stream** out, void* stream) {
+  if (!out) return set_status(UTF8V_EINVAL);
+  std::unique_ptr<utf8v_stream> s(new utf8v_stream);
+  int rc = current_device(&s->dev);
+  if (rc) return rc;
+  hipError_t e = hipMalloc(&s->dstate, 32);
+  if (e == hipSuccess) e = hipHostMalloc(&s->host, 32, hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = utf8v::launch_stream_reset(s->dstate, reinterpret_cast<unsigned long long*>(s->dstate + 1),
+                                   reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    if (s->dstate) (void)hipFree(s->dstate);
+    if (s->host) (void)hipHostFree(s->host);
+    return hip_fail(e);
+  }
+  *out = s.release();
+  return set_status(UTF8V_OK);
+}
+
+int utf8v_stream_update(utf8v_stream* s, const uint8_t* chunk, size_t len, void* stream) {
+  if (!s || (chunk == nullptr && len != 0)) return set_status(UTF8V_EINVAL);
+  if (len == 0) return set_status(UTF8V_OK);
+  int rc = check_device_ptr(chunk);
+  if (rc) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Workspace* ws = nullptr;
+  rc = workspace(st, &ws);
+  if (rc) return rc;
+  const int cus = num_cus_of(s->dev);
+  hipError_t e = utf8v::launch_stream_chunk(chunk, (uint64_t)len, ws->state, s->dstate,
+                                            reinterpret_cast<unsigned long long*>(s->dstate + 1), s->total,
+                                            false, true, tune_single(), cus > 0 ? cus : 1, st);
+  if (e != hipSuccess) return hip_fail(e);
+  s->total += (int64_t)len;
+  return set_status(UTF8V_OK);
+}
+
+int utf8v_stream_finish(utf8v_stream* s, int64_t* first_err, void* stream) {
+  if (!s) return set_status(UTF8V_EINVAL);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Workspace* ws = nullptr;
+  int rc = workspace(st, &ws);
+  if (rc) return rc;
+  const int cus = num_cus_of(s->dev);
+  // the end check at the stream's end, on the history: an empty chunk with the end check,
+  // into its own slot, so the stream can be fed further after a finish
+  hipError_t e = utf8v::launch_stream_chunk(nullptr, 0, ws->state, s->dstate + 2,
+                                            reinterpret_cast<unsigned long long*>(s->dstate + 1), s->total, true,
+                                            false, tune_single(), cus > 0 ? cus : 1, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(s->host, s->dstate, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e);
+  const int64_t r = s->host[0] >= 0 ? s->host[0] : s->host[2];
+  if (first_err) *first_err = r;
+  set_status(UTF8V_OK);
+  return r < 0 ? 1 : 0;
+}
+
+int utf8v_stream_reset(utf8v_stream* s, void* stream) {
+  if (!s) return set_status(UTF8V_EINVAL);
+  hipError_t e = utf8v::launch_stream_reset(s->dstate, reinterpret_cast<unsigned long long*>(s->dstate + 1),
+                                            reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e);
+  s->total = 0;
+  return set_status(UTF8V_OK);
+}
+
+int64_t utf8v_stream_position(const utf8v_stream* s) { return s ? s->total : -1; }
+
+int utf8v_stream_destroy(utf8v_stream* s) {
+  if (!s) return set_status(UTF8V_EINVAL);
+  (void)hipFree(s->dstate);
+  (void)hipHostFree(s->host);
+  delete s;
+  return set_status(UTF8V_OK);
+}
+
 int utf8v_check_offsets(const int64_t* offsets, int64_t n, void* stream) {
   if (n < 0 || offsets == nullptr) return set_status(UTF8V_EINVAL);
   int rc = check_device_ptr(offsets);

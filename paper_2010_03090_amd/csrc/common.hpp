@@ -40,6 +40,11 @@ struct BatchArgs {
 
 hipError_t launch_single(const uint8_t* buf, uint64_t n, unsigned long long* state, int64_t* out,
                          const TuneSingle& cfg, int num_cus, hipStream_t st);
+// One chunk of a stream: history = the 8 bytes before it (updated in place), base =
+// its stream position; without the end check, positions past the chunk do not exist.
+hipError_t launch_stream_chunk(const uint8_t* buf, uint64_t n, unsigned long long* state, int64_t* out,
+                               unsigned long long* hist, int64_t base, bool end_check, bool keep_first,
+                               const TuneSingle& cfg, int num_cus, hipStream_t st);
 BatchArgs batch_args(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* flags, int64_t* first_err,
                      unsigned long long* slot);
 hipError_t launch_batch(const BatchArgs& a, const TuneBatch& cfg, int num_cus, hipStream_t st);
@@ -49,5 +54,6 @@ hipError_t launch_offsets_check(const int64_t* offsets, int64_t n, int* bad, int
 hipError_t launch_classify(const uint8_t* buf, uint64_t n, uint8_t* sc, uint8_t* err, hipStream_t st);
 hipError_t launch_read_ceiling(const uint8_t* buf, uint64_t n, uint32_t* out, int num_cus, hipStream_t st);
 hipError_t launch_copy(const uint8_t* src, uint8_t* dst, uint64_t n, int num_cus, hipStream_t st);
+hipError_t launch_stream_reset(int64_t* first_err, unsigned long long* hist, hipStream_t st);
 
 }  // namespace utf8v

@@ -86,4 +86,17 @@ hipError_t launch_copy(const uint8_t* src, uint8_t* dst, uint64_t n, int num_cus
   return hipGetLastError();
 }
 
+// Stream state {first-error offset, history}: empty stream.
+__global__ void stream_reset(int64_t* first_err, unsigned long long* hist) {
+  if (threadIdx.x == 0) {
+    *first_err = -1;
+    *hist = 0ull;
+  }
+}
+
+hipError_t launch_stream_reset(int64_t* first_err, unsigned long long* hist, hipStream_t st) {
+  hipLaunchKernelGGL(stream_reset, dim3(1), dim3(64), 0, st, first_err, hist);
+  return hipGetLastError();
+}
+
 }  // namespace utf8v

@@ -38,13 +38,30 @@ struct SingleArgs {
   uint64_t tiles, tiles_per_wave;
   unsigned long long* state;  // top word, then kStateGroups group words kStateStride apart
   int64_t* out;               // first-error offset, -1 if valid
+  // Streams (a buffer that continues earlier chunks); a plain buffer has hist = null,
+  // base = 0, end_check = 1, keep_first = 0.
+  unsigned long long* hist;   // the 8 bytes before position 0 (byte 7 = position -1), or null (zeros)
+  int64_t base;               // stream position of byte 0 (offsets written are stream positions)
+  int end_check;              // apply the section 6.3 end check at position n (else positions >= n do not exist)
+  int keep_first;             // leave *out alone if it already holds an error; write no -1
 };
 
-// Dword of bytes [pos-4, pos), zero below position 0.  (buf + pos) is 16-byte aligned.
-__device__ __forceinline__ uint32_t prev_dword(const uint8_t* __restrict__ buf, uint64_t pos) {
-  if (pos >= 4) return *reinterpret_cast<const uint32_t*>(buf + pos - 4);
+// Byte at position p of a buffer whose history (positions -8..-1) is h; zero elsewhere.
+__device__ __forceinline__ uint32_t byte_at(const uint8_t* __restrict__ buf, int64_t n, uint64_t h, int64_t p) {
+  if (p >= 0 && p < n) return buf[p];
+  if (p < 0 && p >= -8) return (uint32_t)(h >> (8 * (8 + p))) & 0xFFu;
+  return 0u;
+}
+
+__device__ __forceinline__ uint64_t history(const SingleArgs& a) { return a.hist ? *a.hist : 0ull; }
+
+// Dword of bytes [pos-4, pos), from the history below position 0.  (buf + pos) is
+// 16-byte aligned.
+__device__ __forceinline__ uint32_t prev_dword(const SingleArgs& a, uint64_t pos) {
+  if (pos >= 4) return *reinterpret_cast<const uint32_t*>(a.buf + pos - 4);
+  const uint64_t h = history(a);
   uint32_t v = 0;
-  for (uint64_t j = 0; j < pos; ++j) v |= (uint32_t)buf[j] << (8 * (4 - pos + j));
+  for (int j = 0; j < 4; ++j) v |= byte_at(a.buf, (int64_t)a.n, h, (int64_t)pos - 4 + j) << (8 * j);
   return v;
 }
 
@@ -123,12 +140,16 @@ __device__ __forceinline__ void single_tile(const u32x4 (&x)[U], uint64_t base, 
 }
 
 // First detection position in the head chunk [i0-16, i0), the tail chunk
-// [i1, i1+16) and at the end (section 6.3), bytes outside the buffer read as zero;
-// kNone if none.  One thread; every byte load is issued before any use.
-__device__ uint64_t edge_detection(const uint8_t* __restrict__ buf, int64_t n, int64_t i0, int64_t i1) {
-  auto byte_at = [&](int64_t p) -> uint32_t { return (p >= 0 && p < n) ? buf[p] : 0u; };
+// [i1, i1+16) and at the end (section 6.3), bytes before position 0 from the
+// history and after the end read as zero; kNone if none.  Without the end check
+// (a stream chunk) positions >= n do not exist yet.  One thread; every byte load
+// is issued before any use.
+__device__ uint64_t edge_detection(const SingleArgs& a) {
+  const int64_t n = (int64_t)a.n, i0 = (int64_t)a.i0, i1 = (int64_t)a.i1;
+  const uint64_t hv = history(a);
   auto dword_at = [&](int64_t p) -> uint32_t {
-    return byte_at(p) | byte_at(p + 1) << 8 | byte_at(p + 2) << 16 | byte_at(p + 3) << 24;
+    return byte_at(a.buf, n, hv, p) | byte_at(a.buf, n, hv, p + 1) << 8 | byte_at(a.buf, n, hv, p + 2) << 16 |
+           byte_at(a.buf, n, hv, p + 3) << 24;
   };
   uint32_t h[5], t[5];
 #pragma unroll
@@ -137,35 +158,40 @@ __device__ uint64_t edge_detection(const uint8_t* __restrict__ buf, int64_t n, i
     t[k] = i1 < n ? dword_at(i1 - 4 + 4 * k) : 0u;
   }
   const uint32_t last = dword_at(n - 4);
+  const int64_t limit = a.end_check ? INT64_MAX : n;  // detections at positions >= limit do not count
   uint64_t d = kNone;
   for (int j = 0; j < 4 && i0 > 0; ++j) {
     const uint32_t e = position_errors(h[j + 1], h[j]);
     if (e) {
       const int64_t p = i0 - 16 + 4 * j + first_byte(e);
-      if (p >= 0) d = (uint64_t)p;
+      if (p >= 0 && p < limit) d = (uint64_t)p;
       break;
     }
   }
   for (int j = 0; j < 4 && i1 < n && d == kNone; ++j) {
     const uint32_t e = position_errors(t[j + 1], t[j]);
     if (e) {
-      d = (uint64_t)(i1 + 4 * j + first_byte(e));
+      const int64_t p = i1 + 4 * j + first_byte(e);
+      if (p < limit) d = (uint64_t)p;
       break;
     }
   }
-  if (n > 0 && open_at_end(last) && (uint64_t)n < d) d = (uint64_t)n;
+  if (a.end_check && open_at_end(last) && (uint64_t)n < d) d = (uint64_t)n;
   return d;
 }
 
 // First detection d -> first-error offset s: the latest k in [d-3, d] at which no
-// character is open (bytes outside the buffer read as zero).
-__device__ int64_t resolve_first_error(const uint8_t* __restrict__ buf, int64_t n, int64_t d) {
+// character is open (bytes before position 0 from the history; the stream starts
+// at position -base).
+__device__ int64_t resolve_first_error(const SingleArgs& a, int64_t d) {
+  const int64_t n = (int64_t)a.n;
+  const uint64_t h = history(a);
   uint32_t w[7];  // w[i] = byte d-i
 #pragma unroll
-  for (int i = 1; i <= 6; ++i) w[i] = (d - i >= 0 && d - i < n) ? buf[d - i] : 0u;
+  for (int i = 1; i <= 6; ++i) w[i] = d - i >= -a.base ? byte_at(a.buf, n, h, d - i) : 0u;
 #pragma unroll
   for (int i = 0; i <= 3; ++i)
-    if (d - i >= 0 && w[i + 1] < 0xC0 && w[i + 2] < 0xE0 && w[i + 3] < 0xF0) return d - i;
+    if (d - i >= -a.base && w[i + 1] < 0xC0 && w[i + 2] < 0xE0 && w[i + 3] < 0xF0) return d - i;
   return d;
 }
 
@@ -207,13 +233,13 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
   }
   __syncthreads();
   uint64_t edge = kNone;  // the last wave (usually the one with the fewest tiles) also checks the edges
-  if (wave == waves - 1 && lane == 0) edge = edge_detection(a.buf, (int64_t)a.n, (int64_t)a.i0, (int64_t)a.i1);
+  if (wave == waves - 1 && lane == 0) edge = edge_detection(a);
   uint64_t t = wave * a.tiles_per_wave;
   const uint64_t t_end = t + a.tiles_per_wave < a.tiles ? t + a.tiles_per_wave : a.tiles;
   uint64_t dmin = kNone;
   if (t < t_end) {
     int ascii_skip = 0;
-    uint32_t carry = prev_dword(a.buf, a.i0 + t * W);
+    uint32_t carry = prev_dword(a, a.i0 + t * W);
     // the buffer's last tile may be partial
     const uint64_t t_full = (t_end == a.tiles && a.i0 + a.tiles * W > a.i1) ? t_end - 1 : t_end;
     if (t < t_full) {
@@ -263,7 +289,16 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
   if ((top >> kStateShift) != groups - 1) return;
   // last group: every workgroup has reported
   const uint64_t pos = (top & kPosNone) < gpos ? (top & kPosNone) : gpos;
-  *a.out = pos == kPosNone ? -1 : resolve_first_error(a.buf, (int64_t)a.n, (int64_t)pos);
+  if (!a.keep_first || *a.out < 0) {
+    if (pos != kPosNone) *a.out = a.base + resolve_first_error(a, (int64_t)pos);
+    else if (!a.keep_first) *a.out = -1;
+  }
+  if (a.hist && a.n > 0) {  // the stream's last 8 bytes, for the next chunk
+    const uint64_t h = *a.hist;
+    uint64_t nh = 0;
+    for (int j = 0; j < 8; ++j) nh |= (uint64_t)byte_at(a.buf, (int64_t)a.n, h, (int64_t)a.n - 8 + j) << (8 * j);
+    *a.hist = nh;
+  }
   atomicExch(a.state, (unsigned long long)kPosNone);
 }
 
@@ -277,6 +312,12 @@ static hipError_t launch_single_t(const SingleArgs& a, int grid, hipStream_t st)
 
 hipError_t launch_single(const uint8_t* buf, uint64_t n, unsigned long long* state, int64_t* out,
                          const TuneSingle& cfg, int num_cus, hipStream_t st) {
+  return launch_stream_chunk(buf, n, state, out, nullptr, 0, true, false, cfg, num_cus, st);
+}
+
+hipError_t launch_stream_chunk(const uint8_t* buf, uint64_t n, unsigned long long* state, int64_t* out,
+                               unsigned long long* hist, int64_t base, bool end_check, bool keep_first,
+                               const TuneSingle& cfg, int num_cus, hipStream_t st) {
   if (n >= kPosNone) return hipErrorInvalidValue;
   const uint64_t mis = (uint64_t)(reinterpret_cast<uintptr_t>(buf) & 15);
   const uint64_t i0 = mis ? 16 - mis : 0;
@@ -286,6 +327,7 @@ hipError_t launch_single(const uint8_t* buf, uint64_t n, unsigned long long* sta
   const uint64_t W = (uint64_t)U * 1024;
   SingleArgs a;
   a.buf = buf; a.n = n; a.i0 = i0; a.i1 = i1; a.state = state; a.out = out;
+  a.hist = hist; a.base = base; a.end_check = end_check ? 1 : 0; a.keep_first = keep_first ? 1 : 0;
   a.tiles = i1 > i0 ? (i1 - i0 + W - 1) / W : 0;
   const uint64_t max_waves = (uint64_t)num_cus * (uint64_t)cfg.waves_per_cu;
   a.tiles_per_wave = (a.tiles + max_waves - 1) / max_waves;

@@ -383,3 +383,52 @@ def test_pageable_host_pointer_rejected(u8):
     buf = ctypes.create_string_buffer(b"abc")
     lib = u8.load()
     assert lib.utf8v_validate_ex(ctypes.addressof(buf), 3, None, None) == -2
+
+
+def test_stream_any_split_equals_whole(u8):
+    """Chunked validation: every split (inside characters, empty and 1-byte chunks) equals the whole."""
+    rng = np.random.default_rng(23)
+    wholes = []
+    for v in ("mixed", "emoji", "cjk"):
+        b = synth.text(200_003, v, 30)
+        wholes.append(b.copy())
+        for cls in range(7):
+            c = b.copy()
+            synth.inject(c, int(rng.integers(0, c.size)), cls, cls + 1)
+            wholes.append(c)
+    wholes.append(rng.integers(0, 256, 50_000, dtype=np.uint8))
+    t = synth.text(9_999, "emoji", 31)
+    wholes.append(t[:-1].copy())                      # cut inside the last character
+    for n in range(0, 8):
+        wholes.append(synth.text(n, "mixed", 40 + n))
+    wholes.append(np.array([0xE2, 0x82], np.uint8))   # incomplete, then more later
+    for i, whole in enumerate(wholes):
+        exp = oracle.first_error(whole)
+        td = dev(whole) if whole.size else torch.empty(0, dtype=torch.uint8, device="cuda")
+        for trial in range(4):
+            say(f"case: stream whole {i} ({whole.size} B) split {trial}")
+            k = int(rng.integers(1, 12))
+            cuts = np.sort(rng.integers(0, whole.size + 1, k)) if whole.size else np.zeros(k, np.int64)
+            if trial == 3 and whole.size:
+                cuts = np.unique(np.concatenate([cuts, np.arange(0, min(whole.size, 9))]))  # 1-byte chunks
+            bounds = [0] + cuts.tolist() + [whole.size]
+            with u8.Stream() as s:
+                for a, b in zip(bounds[:-1], bounds[1:]):
+                    s.update(td[a:b])
+                assert s.position == whole.size
+                assert s.finish() == exp, (i, trial, bounds[:6])
+
+
+def test_stream_finish_then_continue(u8):
+    """A finish reports the prefix; feeding more and finishing again reports the longer stream."""
+    ok = "x€y😀".encode()
+    part = np.frombuffer(ok[:3], np.uint8)     # "x" and two of the euro sign's three bytes
+    rest = np.frombuffer(ok[3:], np.uint8)
+    with u8.Stream() as s:
+        s.update(dev(part))
+        assert s.finish() == oracle.first_error(part) == 1
+        s.update(dev(rest))
+        assert s.finish() == -1 == oracle.first_error(np.frombuffer(ok, np.uint8))
+        s.reset()
+        s.update(dev(np.frombuffer(b"\xff", np.uint8)))
+        assert s.finish() == 0
