@@ -10,6 +10,10 @@ Two independent references live here:
   Algorithm 1 (section 4) over the byte ranges of Table 1 (section 2), written
   in C (``utf8_oracle.c``).  It returns the first-error offset: the length of
   the longest valid prefix made of whole characters, or -1 for valid input.
+* ``error_class`` / ``error_class_batch`` -- which of the six rules of section 3
+  (a..f, coded 1..6) the first ill-formed character breaks: malformed rules
+  first (5+ byte, too long, too short), then overlong / too large / surrogate
+  on the decoded code point.
 * ``lookup_model`` -- the paper's lookup algorithm (section 6) written out step
   by step in numpy, with its three nibble tables derived from the error
   patterns of Table 8.  It is pinned to the worked example of Table 9.
@@ -47,6 +51,11 @@ def _load():
         lib.oracle_first_error_batch.restype = ctypes.c_int
         lib.oracle_first_error_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        lib.oracle_error_class.restype = ctypes.c_int
+        lib.oracle_error_class.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64]
+        lib.oracle_error_class_batch.restype = ctypes.c_int
+        lib.oracle_error_class_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                                 ctypes.c_void_p, ctypes.c_void_p]
         lib.oracle_exhaustive_hist.restype = ctypes.c_int
         lib.oracle_exhaustive_hist.argtypes = [ctypes.c_int, ctypes.c_void_p]
         _lib = lib
@@ -66,6 +75,28 @@ def first_error(buf) -> int:
     """First-error offset of one byte string (-1 if it is valid UTF-8)."""
     a = _as_u8(buf)
     return int(_load().oracle_first_error(a.ctypes.data if a.size else None, a.size))
+
+
+ERROR_CLASSES = {0: "valid", 1: "five_plus_byte", 2: "too_short", 3: "too_long", 4: "overlong",
+                 5: "too_large", 6: "surrogate"}
+
+
+def error_class(buf, first_err: int | None = None) -> int:
+    """Section 3 rule (1..6 = a..f) broken by the first ill-formed character, 0 if valid."""
+    a = _as_u8(buf)
+    s = first_error(a) if first_err is None else int(first_err)
+    return int(_load().oracle_error_class(a.ctypes.data if a.size else None, a.size, s))
+
+
+def error_class_batch(data, offsets, first_err) -> np.ndarray:
+    d = _as_u8(data)
+    o = np.ascontiguousarray(offsets, dtype=np.int64)
+    f = np.ascontiguousarray(first_err, dtype=np.int64)
+    out = np.zeros(o.size - 1, dtype=np.uint8)
+    if _load().oracle_error_class_batch(d.ctypes.data if d.size else None, o.ctypes.data, o.size - 1,
+                                        f.ctypes.data, out.ctypes.data):
+        raise ValueError("bad batch")
+    return out
 
 
 def is_valid(buf) -> bool:

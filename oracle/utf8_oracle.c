@@ -118,6 +118,53 @@ int oracle_first_error_batch(const uint8_t *data, const int64_t *offsets, int64_
 }
 
 /*
+ * Error class of the ill-formed character starting at b[s] (s = a first-error
+ * offset, 0 <= s < n), by the six rules of section 3, taken in this order:
+ *   1  a) 5+ byte   -- the lead byte has five or more header bits (F8..FF);
+ *   3  c) too long  -- the lead byte is a continuation byte (80..BF);
+ *   2  b) too short -- the lead's header bits announce N bytes (C0..DF: 2,
+ *                      E0..EF: 3, F0..F7: 4) but fewer than N-1 continuation
+ *                      bytes follow before another byte or the end;
+ * and, for a well-formed sequence, on its decoded code point:
+ *   4  d) overlong  -- below the smallest value of its length (80, 800, 10000);
+ *   5  e) too large -- above U+10FFFF;
+ *   6  f) surrogate -- in U+D800..DFFF.
+ * The malformed rules come first because only a well-formed sequence decodes to
+ * a code point.  Returns 0 if s is out of range or the character is valid.
+ * Codes: 1..6 = rules a..f.
+ */
+int oracle_error_class(const uint8_t *b, int64_t n, int64_t s)
+{
+    if (s < 0 || s >= n) return 0;
+    uint8_t c = b[s];
+    if (c >= 0xF8) return 1;                                   /* a) five or more header bits */
+    if (c >= 0x80 && c <= 0xBF) return 3;                      /* c) continuation as lead */
+    if (c <= 0x7F) return 0;                                   /* ASCII is always valid */
+    int len = c >= 0xF0 ? 4 : c >= 0xE0 ? 3 : 2;
+    for (int k = 1; k < len; k++)
+        if (s + k >= n || !in_range(b[s + k], 0x80, 0xBF)) return 2;   /* b) too short */
+    uint32_t cp = (uint32_t)(c & (0x7F >> len));               /* payload bits of the lead */
+    for (int k = 1; k < len; k++) cp = (cp << 6) | (b[s + k] & 0x3F);
+    static const uint32_t min_cp[5] = {0, 0, 0x80, 0x800, 0x10000};
+    if (cp < min_cp[len]) return 4;                            /* d) overlong */
+    if (cp > 0x10FFFF) return 5;                               /* e) too large */
+    if (cp >= 0xD800 && cp <= 0xDFFF) return 6;                /* f) surrogate */
+    return 0;
+}
+
+/* Error class per string of a CSR batch, from its first-error offset (0 for valid strings). */
+int oracle_error_class_batch(const uint8_t *data, const int64_t *offsets, int64_t n, const int64_t *first_err,
+                             uint8_t *out)
+{
+    if (n < 0) return -1;
+    for (int64_t k = 0; k < n; k++) {
+        int64_t st = offsets[k], len = offsets[k + 1] - st;
+        out[k] = (uint8_t)(first_err[k] < 0 ? 0 : oracle_error_class(data + st, len, first_err[k]));
+    }
+    return 0;
+}
+
+/*
  * Brute force over every byte string of length len (len <= 4): hist[k] counts
  * the strings whose first-error offset is k (0 <= k < len) and hist[len] counts
  * the valid ones.

@@ -4,6 +4,8 @@ None of these re-derive the oracle's own code: they use the closed-form counts
 implied by Table 1, the paper's labelled examples, CPython's strict UTF-8
 decoder, a decode/re-encode invariant, and sweeps of every code point.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -243,3 +245,91 @@ def test_batch_matches_single_and_relative_offsets():
     for k, s in enumerate(strs):
         assert ferr[k] == oracle.first_error(s)
         assert flags[k] == (ferr[k] < 0)
+
+
+# ---- error classes (section 3 rules a..f) ------------------------------------------------
+
+
+def _golden_classes():
+    rows = []
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "error_classes.txt")
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        hx, off, cls, label, src = [x.strip() for x in line.split("|")]
+        rows.append((bytes.fromhex(hx), int(off), int(cls), label))
+    return rows
+
+
+def test_error_class_of_the_papers_examples():
+    for b, off, cls, label in _golden_classes():
+        assert oracle.first_error(b) == off, label
+        assert oracle.error_class(b) == cls, label
+
+
+def _encode(cp: int, nbytes: int) -> bytes:
+    """cp in nbytes UTF-8 form, whatever its value (overlong, surrogate or too large allowed)."""
+    if nbytes == 1:
+        return bytes([cp])
+    lead = (0xFF << (8 - nbytes)) & 0xFF
+    out = [0x80 | ((cp >> (6 * k)) & 0x3F) for k in range(nbytes - 1)][::-1]
+    return bytes([lead | (cp >> (6 * (nbytes - 1)))] + out)
+
+
+def test_error_class_by_code_point():
+    """Every surrogate, overlong and too-large form, built by an encoder, gets its rule."""
+    for cp in range(0xD800, 0xE000):
+        assert oracle.error_class(_encode(cp, 3)) == 6
+    for cp in range(0, 0x80):
+        assert oracle.error_class(_encode(cp, 2)) == 4
+    for cp in range(0, 0x800, 7):
+        assert oracle.error_class(_encode(cp, 3)) == 4
+    for cp in range(0, 0x10000, 97):
+        assert oracle.error_class(_encode(cp, 4)) == 4
+    for cp in range(0x110000, 0x200000, 1009):
+        assert oracle.error_class(_encode(cp, 4)) == 5
+    for cp in (0x80, 0x7FF, 0x800, 0xFFFF, 0x10000, 0x10FFFF, 0xE000, 0xD7FF):
+        n = 1 if cp < 0x80 else 2 if cp < 0x800 else 3 if cp < 0x10000 else 4
+        b = _encode(cp, n)
+        assert oracle.error_class(b) == 0
+        for cut in range(1, n):                   # truncated: too short
+            assert oracle.error_class(b[:cut]) == 2
+        assert oracle.error_class(b[:1] + b"A" + b[2:]) == 2 if n > 1 else True
+    for lead in range(0x80, 0xC0):                # stray continuation: too long
+        assert oracle.error_class(bytes([lead, 0x41])) == 3
+    for lead in range(0xF8, 0x100):               # five or more header bits
+        assert oracle.error_class(bytes([lead]) + b"\x80" * 5) == 1
+
+
+def test_error_class_agrees_with_cpython_reasons():
+    """CPython's decoder reason narrows the class: start byte, continuation byte or end of data.
+
+    CPython rejects C0, C1 and F5..F7 as start bytes outright; by the section 3
+    rules they are too short when their continuations are missing, else overlong
+    (C0, C1) or too large (F5..F7).
+    """
+    cont = {2, 4, 5, 6}            # a bad second/third/fourth byte
+    alpha = [0x00, 0x41, 0x7F, 0x80, 0x8F, 0x90, 0x9F, 0xA0, 0xBF, 0xC0, 0xC1, 0xC2, 0xDF, 0xE0, 0xE1, 0xEC,
+             0xED, 0xEE, 0xEF, 0xF0, 0xF1, 0xF3, 0xF4, 0xF5, 0xF7, 0xF8, 0xFF]
+    import itertools
+    for n in (1, 2, 3, 4):
+        for t in itertools.product(alpha, repeat=n):
+            b = bytes(t)
+            s = oracle.first_error(b)
+            cls = oracle.error_class(b, s)
+            try:
+                b.decode("utf-8")
+                assert s == -1 and cls == 0
+                continue
+            except UnicodeDecodeError as e:
+                assert e.start == s and cls != 0
+                if e.reason == "invalid start byte":
+                    lead = b[s]
+                    want = {3} if 0x80 <= lead <= 0xBF else {1} if lead >= 0xF8 else \
+                        {2, 4} if lead in (0xC0, 0xC1) else {2, 5}
+                    assert cls in want, (b.hex(), cls)
+                elif e.reason == "invalid continuation byte":
+                    assert cls in cont, (b.hex(), cls)
+                else:
+                    assert e.reason == "unexpected end of data" and cls == 2, (b.hex(), cls)

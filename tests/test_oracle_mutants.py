@@ -87,3 +87,72 @@ def test_unmutated_oracle_passes(tmp_path):
 def test_mutant_is_caught(tmp_path, name):
     old, new = MUTANTS[name]
     assert not _pins_hold(_build(tmp_path, name, old, new)), f"pins missed mutant: {name}"
+
+
+# ---- the error-class rule ----------------------------------------------------------------
+
+CLASS_MUTANTS = {
+    "five-plus boundary at FC": ("if (c >= 0xF8) return 1;", "if (c >= 0xFC) return 1;"),
+    "surrogate range short by one": ("cp <= 0xDFFF) return 6;", "cp < 0xDFFF) return 6;"),
+    "three-byte overlong limit off by one": ("0x80, 0x800, 0x10000}", "0x80, 0x7FF, 0x10000}"),
+    "too-large limit at 1FFFFF": ("if (cp > 0x10FFFF) return 5;", "if (cp > 0x1FFFFF) return 5;"),
+    "last continuation unchecked": ("for (int k = 1; k < len; k++)\n        if (s + k >= n",
+                                    "for (int k = 1; k < len - 1; k++)\n        if (s + k >= n"),
+    "lead payload bit dropped": ("(c & (0x7F >> len))", "(c & (0x7F >> (len + 1)))"),
+    "too large reported as surrogate": ("return 5;                               /* e)",
+                                        "return 6;                               /* e)"),
+}
+
+
+def _class_pins_hold(lib):
+    import itertools
+
+    import test_oracle as to
+    f = lib.oracle_first_error
+    c = lib.oracle_error_class
+    for b, off, cls, _ in to._golden_classes():
+        if f(b, len(b)) != off or c(b, len(b), off) != cls:
+            return False
+    checks = [(to._encode(cp, 3), 6) for cp in range(0xD800, 0xE000, 31)] + [(to._encode(0xDFFF, 3), 6)]
+    checks += [(to._encode(cp, 2), 4) for cp in range(0, 0x80, 5)]
+    checks += [(to._encode(cp, 3), 4) for cp in range(0, 0x800, 37)] + [(to._encode(0x7FF, 3), 4)]
+    checks += [(to._encode(cp, 4), 5) for cp in range(0x110000, 0x200000, 4099)]
+    checks += [(to._encode(cp, 4), 0) for cp in (0x10000, 0x10FFFF)] + [(to._encode(0x800, 3), 0)]
+    for b, cls in checks:
+        s = f(b, len(b))
+        if (c(b, len(b), s) if s >= 0 else 0) != cls:
+            return False
+    alpha = [0x00, 0x41, 0x80, 0xBF, 0xC0, 0xC2, 0xE0, 0xED, 0xF0, 0xF4, 0xF5, 0xF8, 0xFF, 0x90, 0xA0]
+    for n in (1, 2, 3):
+        for t in itertools.product(alpha, repeat=n):
+            b = bytes(t)
+            s = f(b, n)
+            cls = c(b, n, s) if s >= 0 else 0
+            try:
+                b.decode("utf-8")
+                ok = s == -1
+            except UnicodeDecodeError as e:
+                ok = e.start == s and cls != 0
+                if e.reason == "unexpected end of data":
+                    ok = ok and cls == 2
+            if not ok:
+                return False
+    return True
+
+
+def _build_classes(tmp_path, name, old, new):
+    lib = _build(tmp_path, name, old, new)
+    lib.oracle_error_class.restype = ctypes.c_int
+    lib.oracle_error_class.argtypes = [ctypes.c_char_p, ctypes.c_int64, ctypes.c_int64]
+    return lib
+
+
+def test_unmutated_class_rule_passes(tmp_path):
+    marker = "int oracle_error_class("
+    assert _class_pins_hold(_build_classes(tmp_path, "same", marker, marker))
+
+
+@pytest.mark.parametrize("name", sorted(CLASS_MUTANTS))
+def test_class_mutant_is_caught(tmp_path, name):
+    old, new = CLASS_MUTANTS[name]
+    assert not _class_pins_hold(_build_classes(tmp_path, name, old, new)), f"pins missed mutant: {name}"
