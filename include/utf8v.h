@@ -104,6 +104,42 @@ int utf8v_validate_batch_async(const uint8_t *data, const int64_t *offsets, int6
 int utf8v_validate_batch_graph(const uint8_t *data, const int64_t *offsets, int64_t n,
                                uint8_t *out_flags, int64_t *out_first_err, void *stream);
 
+/* ---- error classes ------------------------------------------------------------------ */
+
+/*
+ * Which rule of section 3 the first ill-formed character breaks, from a
+ * first-error offset computed by the functions above:
+ *   UTF8V_CLASS_NONE 0 (valid), 1 five or more header bits (rule a), 2 too short
+ *   (rule b), 3 too long (rule c), 4 overlong (rule d), 5 too large (rule e),
+ *   6 surrogate (rule f).
+ * A character can break several rules (C0 alone is both a two-byte lead without
+ * its continuation and an overlong lead); the malformed rules a, c, b rank first,
+ * because only a complete sequence decodes to a code point, then d, e, f.
+ */
+#define UTF8V_CLASS_NONE 0
+#define UTF8V_CLASS_FIVE_PLUS 1
+#define UTF8V_CLASS_TOO_SHORT 2
+#define UTF8V_CLASS_TOO_LONG 3
+#define UTF8V_CLASS_OVERLONG 4
+#define UTF8V_CLASS_TOO_LARGE 5
+#define UTF8V_CLASS_SURROGATE 6
+
+/*
+ * utf8v_error_class -- enqueue: *dev_class (device uint8) = class of buf's
+ * first error, given its first-error offset in *dev_first_err (device int64, as
+ * written by utf8v_validate_async).
+ */
+int utf8v_error_class(const uint8_t *buf, size_t len, const int64_t *dev_first_err, uint8_t *dev_class,
+                      void *stream);
+
+/*
+ * utf8v_error_classes -- enqueue: out_class[k] = class of string k's first
+ * error, from first_err[k] as written by the batch functions (relative offsets,
+ * -1 = valid).  All arrays in device memory; n == 0 is a no-op.
+ */
+int utf8v_error_classes(const uint8_t *data, const int64_t *offsets, int64_t n, const int64_t *first_err,
+                        uint8_t *out_class, void *stream);
+
 /* ---- streams: one byte sequence fed in chunks --------------------------------------- */
 
 /*

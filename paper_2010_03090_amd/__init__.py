@@ -17,7 +17,7 @@ from . import _native
 from ._native import Config, Utf8vError, check, load
 
 __all__ = ["validate", "first_error", "validate_async", "validate_batch", "validate_batch_async",
-           "validate_batch_graph", "Stream",
+           "validate_batch_graph", "Stream", "error_class", "error_classes", "ERROR_CLASSES",
            "classify", "check_offsets", "get_config", "set_config", "num_cus", "read_ceiling", "copy",
            "Config", "Utf8vError", "load"]
 
@@ -106,6 +106,34 @@ def validate_batch(data, offsets, stream=None):
     ferr = torch.empty(max(n, 0), dtype=torch.int64, device=offsets.device)
     validate_batch_async(data, offsets, flags, ferr, stream)
     return flags, ferr
+
+
+ERROR_CLASSES = {0: "valid", 1: "five_plus_byte", 2: "too_short", 3: "too_long", 4: "overlong",
+                 5: "too_large", 6: "surrogate"}
+
+
+def error_class(buf, stream=None) -> int:
+    """Section 3 rule (1..6 = a..f) broken by buf's first ill-formed character, 0 if valid. Synchronizes."""
+    torch = _torch()
+    _dev_u8(buf)
+    fe = torch.empty(1, dtype=torch.int64, device=buf.device)
+    cls = torch.empty(1, dtype=torch.uint8, device=buf.device)
+    validate_async(buf, fe, stream)
+    check(load().utf8v_error_class(buf.data_ptr() if buf.numel() else None, buf.numel(), fe.data_ptr(),
+                                   cls.data_ptr(), _stream_handle(stream)), "utf8v_error_class")
+    return int(cls.item())
+
+
+def error_classes(data, offsets, first_err, stream=None):
+    """Per-string class (uint8 tensor on the device) from a batch's first-error offsets."""
+    torch = _torch()
+    n = offsets.numel() - 1
+    out = torch.empty(max(n, 0), dtype=torch.uint8, device=offsets.device)
+    if n > 0:
+        check(load().utf8v_error_classes(data.data_ptr() if data.numel() else offsets.data_ptr(),
+                                         offsets.data_ptr(), n, first_err.data_ptr(), out.data_ptr(),
+                                         _stream_handle(stream)), "utf8v_error_classes")
+    return out
 
 
 class Stream:

@@ -365,6 +365,42 @@ int utf8v_stream_destroy(utf8v_stream* s) {
   return set_status(UTF8V_OK);
 }
 
+int utf8v_error_class(const uint8_t* buf, size_t len, const int64_t* dev_first_err, uint8_t* dev_class,
+                      void* stream) {
+  if ((buf == nullptr && len != 0) || !dev_first_err || !dev_class) return set_status(UTF8V_EINVAL);
+  for (const void* p : {(const void*)dev_first_err, (const void*)dev_class}) {
+    int rc = check_device_ptr(p);
+    if (rc) return rc;
+  }
+  if (len != 0) {
+    int rc = check_device_ptr(buf);
+    if (rc) return rc;
+  }
+  hipError_t e = utf8v::launch_error_class_one(buf, (int64_t)len, dev_first_err, dev_class,
+                                               reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e);
+  return set_status(UTF8V_OK);
+}
+
+int utf8v_error_classes(const uint8_t* data, const int64_t* offsets, int64_t n, const int64_t* first_err,
+                        uint8_t* out_class, void* stream) {
+  if (n < 0) return set_status(UTF8V_EINVAL);
+  if (n == 0) return set_status(UTF8V_OK);
+  if (!data || !offsets || !first_err || !out_class) return set_status(UTF8V_EINVAL);
+  for (const void* p : {(const void*)data, (const void*)offsets, (const void*)first_err, (const void*)out_class}) {
+    int rc = check_device_ptr(p);
+    if (rc) return rc;
+  }
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  const int cus = num_cus_of(dev);
+  hipError_t e = utf8v::launch_error_classes(data, offsets, n, first_err, out_class, cus > 0 ? cus : 1,
+                                             reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e);
+  return set_status(UTF8V_OK);
+}
+
 int utf8v_check_offsets(const int64_t* offsets, int64_t n, void* stream) {
   if (n < 0 || offsets == nullptr) return set_status(UTF8V_EINVAL);
   int rc = check_device_ptr(offsets);

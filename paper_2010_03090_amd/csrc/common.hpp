@@ -55,5 +55,9 @@ hipError_t launch_classify(const uint8_t* buf, uint64_t n, uint8_t* sc, uint8_t*
 hipError_t launch_read_ceiling(const uint8_t* buf, uint64_t n, uint32_t* out, int num_cus, hipStream_t st);
 hipError_t launch_copy(const uint8_t* src, uint8_t* dst, uint64_t n, int num_cus, hipStream_t st);
 hipError_t launch_stream_reset(int64_t* first_err, unsigned long long* hist, hipStream_t st);
+hipError_t launch_error_classes(const uint8_t* data, const int64_t* offsets, int64_t n, const int64_t* first_err,
+                                uint8_t* out, int num_cus, hipStream_t st);
+hipError_t launch_error_class_one(const uint8_t* buf, int64_t len, const int64_t* first_err, uint8_t* out,
+                                  hipStream_t st);
 
 }  // namespace utf8v

@@ -86,6 +86,55 @@ hipError_t launch_copy(const uint8_t* src, uint8_t* dst, uint64_t n, int num_cus
   return hipGetLastError();
 }
 
+// Which rule of section 3 the ill-formed character starting at b[s] breaks
+// (b = one string of len bytes): 1 five or more header bits, 2 too short, 3 too
+// long, 4 overlong, 5 too large, 6 surrogate; 0 if s is not an error position.
+// Malformed sequences (1-3) rank first: only a complete sequence has a code
+// point.  The code point rules are read off the lead and second byte ranges.
+__device__ uint8_t class_at(const uint8_t* __restrict__ b, int64_t len, int64_t s) {
+  if (s < 0 || s >= len) return 0;
+  const uint32_t c = b[s];
+  if (c < 0x80) return 0;
+  if (c < 0xC0) return 3;
+  if (c >= 0xF8) return 1;
+  const int need = c >= 0xF0 ? 3 : c >= 0xE0 ? 2 : 1;  // continuation bytes the header announces
+  for (int k = 1; k <= need; ++k)
+    if (s + k >= len || (b[s + k] & 0xC0u) != 0x80u) return 2;
+  const uint32_t b1 = b[s + 1];
+  if (c <= 0xC1 || (c == 0xE0 && b1 < 0xA0) || (c == 0xF0 && b1 < 0x90)) return 4;
+  if (c >= 0xF5 || (c == 0xF4 && b1 >= 0x90)) return 5;
+  if (c == 0xED && b1 >= 0xA0) return 6;
+  return 0;
+}
+
+__global__ void error_classes(const uint8_t* __restrict__ data, const int64_t* __restrict__ offsets, int64_t n,
+                              const int64_t* __restrict__ first_err, uint8_t* __restrict__ out) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = first_err[k];
+    out[k] = s < 0 ? 0 : class_at(data + offsets[k], offsets[k + 1] - offsets[k], s);
+  }
+}
+
+__global__ void error_class_one(const uint8_t* __restrict__ buf, int64_t len, const int64_t* __restrict__ first_err,
+                                uint8_t* __restrict__ out) {
+  if (threadIdx.x == 0) *out = class_at(buf, len, *first_err);
+}
+
+hipError_t launch_error_classes(const uint8_t* data, const int64_t* offsets, int64_t n, const int64_t* first_err,
+                                uint8_t* out, int num_cus, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > (int64_t)num_cus * 8) blocks = (int64_t)num_cus * 8;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(error_classes, dim3((unsigned)blocks), dim3(256), 0, st, data, offsets, n, first_err, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_error_class_one(const uint8_t* buf, int64_t len, const int64_t* first_err, uint8_t* out,
+                                  hipStream_t st) {
+  hipLaunchKernelGGL(error_class_one, dim3(1), dim3(64), 0, st, buf, len, first_err, out);
+  return hipGetLastError();
+}
+
 // Stream state {first-error offset, history}: empty stream.
 __global__ void stream_reset(int64_t* first_err, unsigned long long* hist) {
   if (threadIdx.x == 0) {

@@ -432,3 +432,54 @@ def test_stream_finish_then_continue(u8):
         s.reset()
         s.update(dev(np.frombuffer(b"\xff", np.uint8)))
         assert s.finish() == 0
+
+
+def _golden_class_rows():
+    import os
+    rows = []
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "error_classes.txt")
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            hx, off, cls, label, _ = [x.strip() for x in line.split("|")]
+            rows.append((np.frombuffer(bytes.fromhex(hx), np.uint8), int(off), int(cls), label))
+    return rows
+
+
+def test_error_class_paper_examples(u8):
+    for b, off, cls, label in _golden_class_rows():
+        say(f"case: error class {label}")
+        assert u8.first_error(dev(b)) == off, label
+        assert u8.error_class(dev(b)) == cls, label
+
+
+def test_error_classes_batch_exhaustive_and_mixed(u8):
+    """Classes of every string of length <= 3, of a labelled mix, and of the 1M-string batch."""
+    parts, lens = [], []
+    for n in range(1, 4):
+        v = np.arange(256 ** n, dtype=np.uint32)
+        strs = np.stack([(v >> (8 * k)) & 0xFF for k in range(n)], 1).astype(np.uint8)
+        parts.append(strs.reshape(-1))
+        lens += [n] * strs.shape[0]
+    cases = [(np.concatenate(parts), np.concatenate([[0], np.cumsum(lens)]).astype(np.int64))]
+    data, offsets, _ = synth.lognormal_batch(1_000_000, 2)
+    cases.append((data, offsets))
+    rng = np.random.default_rng(3)
+    lens = rng.integers(0, 9, 100_000)
+    cases.append((rng.integers(0, 256, int(lens.sum()), dtype=np.uint8),
+                  np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)))
+    for i, (data, offsets) in enumerate(cases):
+        say(f"case: error classes batch {i} ({offsets.size - 1} strings)")
+        f_o, e_o = oracle.first_error_batch(data, offsets)
+        c_o = oracle.error_class_batch(data, offsets, e_o)
+        td, to = dev(data), dev(offsets)
+        flags, ferr = u8.validate_batch(td, to)
+        cls = u8.error_classes(td, to, ferr)
+        torch.cuda.synchronize()
+        assert np.array_equal(ferr.cpu().numpy(), e_o)
+        got = cls.cpu().numpy()
+        assert np.array_equal(got, c_o), np.nonzero(got != c_o)[0][:10]
+        if i == 0:   # no string of three bytes holds a complete four-byte sequence: no class 5
+            assert set(np.unique(c_o).tolist()) == {0, 1, 2, 3, 4, 6}
+        if i == 1:   # the injected error kinds reach every class but 5+ byte leads alone
+            assert {2, 3, 4, 5, 6} <= set(np.unique(c_o).tolist())
