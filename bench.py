@@ -65,6 +65,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="skip the graph / small-batch launch comparison")
     ap.add_argument("--no-heavy", action="store_true", help="skip the heavy-tail batches")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
+    ap.add_argument("--no-copy", action="store_true", help="skip the fused copy + validate part")
     ap.add_argument("--serve-loads", default="10000,50000,200000", help="offered loads, requests/s")
     ap.add_argument("--serve-requests", type=int, default=100_000, help="measured requests per load")
     ap.add_argument("--serve-baseline-requests", type=int, default=20_000,
@@ -103,6 +104,10 @@ def main():
     # ---- batched: 1M log-normal strings vs one launch per string ------------------------------
     if not args.no_batch:
         result["batched"] = bench_batch(u8, lib, synth, torch, dev, stream, sh, args)
+
+    # ---- fused copy + validate (device to device, pinned host to device) ----------------------
+    if not args.no_copy:
+        result["copy_validate"] = bench_copy(u8, synth, torch, dev, stream, args)
 
     # ---- heavy-tail batches: 20,000 Pareto strings, ~125 MiB and ~4 GiB ------------------------
     if not args.no_batch and not args.no_heavy:
@@ -442,6 +447,57 @@ def bench_graph(u8, lib, torch, td, to, flags, ferr, nstr, offsets, expected, st
                 raise SystemExit(f"wrong {name} small-batch result")
         out[f"n{n}"] = row
     return out
+
+
+def bench_copy(u8, synth, torch, dev, stream, args):
+    """1 GiB of CJK-like text: copy alone, validate alone, copy then validate, and the fused pass;
+    from device memory and from pinned host memory."""
+    n = GIB
+    h = synth.text(n, "cjk", 3)
+    src_d = torch.from_numpy(h).to(dev)
+    src_h = torch.from_numpy(h).pin_memory()
+    dst = torch.empty(n, dtype=torch.uint8, device=dev)
+    out = torch.empty(2, dtype=torch.int64, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    reps = max(5, args.steps // 2)
+    t_w = time.perf_counter()
+    while time.perf_counter() - t_w < args.warmup_seconds:
+        u8.copy_validate(src_d, dst, out[0:1])
+        torch.cuda.synchronize()
+    row = {"bytes": n}
+    t_copy = timed(lambda: u8.copy(src_d, dst), reps)
+    t_val = timed(lambda: u8.validate_async(src_d, out[1:2]), reps)
+    t_both = timed(lambda: (u8.copy(src_d, dst), u8.validate_async(src_d, out[1:2])), reps)
+    t_fused = timed(lambda: u8.copy_validate(src_d, dst, out[0:1]), reps)
+    if int(out[0]) != -1 or not torch.equal(dst[-4096:], src_d[-4096:]):
+        raise SystemExit("wrong copy_validate result")
+    row["device_to_device_GBps"] = {"copy": round(n / t_copy / 1e9, 1), "validate": round(n / t_val / 1e9, 1),
+                                    "copy_then_validate": round(n / t_both / 1e9, 1),
+                                    "fused": round(n / t_fused / 1e9, 1)}
+    t_h2d = timed(lambda: dst.copy_(src_h, non_blocking=True), 3)
+    t_h2d_val = timed(lambda: (dst.copy_(src_h, non_blocking=True), u8.validate_async(dst, out[1:2])), 3)
+    t_h_fused = timed(lambda: u8.copy_validate(src_h, dst, out[0:1]), 3)
+    if int(out[0]) != -1:
+        raise SystemExit("wrong host copy_validate result")
+    row["pinned_host_to_device_GBps"] = {"copy": round(n / t_h2d / 1e9, 1),
+                                         "copy_then_validate": round(n / t_h2d_val / 1e9, 1),
+                                         "fused": round(n / t_h_fused / 1e9, 1)}
+    log(f"copy+validate GB/s: {row}")
+    del src_d, src_h, dst
+    torch.cuda.empty_cache()
+    return row
 
 
 def bench_heavy(u8, lib, synth, torch, dev, stream, sh, args):

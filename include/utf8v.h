@@ -104,6 +104,16 @@ int utf8v_validate_batch_async(const uint8_t *data, const int64_t *offsets, int6
 int utf8v_validate_batch_graph(const uint8_t *data, const int64_t *offsets, int64_t n,
                                uint8_t *out_flags, int64_t *out_first_err, void *stream);
 
+/*
+ * utf8v_copy_validate -- enqueue one pass that copies src[0..len) to dst and
+ * validates it (first-error offset to *dev_first_err, as utf8v_validate_async):
+ * every byte is read once, for both jobs.  src may be device memory or pinned
+ * host memory (then this is a validating host-to-device copy over PCIe); dst
+ * device memory.  dst and src must have the same address modulo 16 and must not
+ * overlap (else UTF8V_EINVAL).
+ */
+int utf8v_copy_validate(uint8_t *dst, const uint8_t *src, size_t len, int64_t *dev_first_err, void *stream);
+
 /* ---- error classes ------------------------------------------------------------------ */
 
 /*

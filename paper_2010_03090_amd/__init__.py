@@ -17,7 +17,7 @@ from . import _native
 from ._native import Config, Utf8vError, check, load
 
 __all__ = ["validate", "first_error", "validate_async", "validate_batch", "validate_batch_async",
-           "validate_batch_graph", "Stream", "error_class", "error_classes", "ERROR_CLASSES",
+           "validate_batch_graph", "Stream", "error_class", "error_classes", "ERROR_CLASSES", "copy_validate",
            "classify", "check_offsets", "get_config", "set_config", "num_cus", "read_ceiling", "copy",
            "Config", "Utf8vError", "load"]
 
@@ -106,6 +106,22 @@ def validate_batch(data, offsets, stream=None):
     ferr = torch.empty(max(n, 0), dtype=torch.int64, device=offsets.device)
     validate_batch_async(data, offsets, flags, ferr, stream)
     return flags, ferr
+
+
+def copy_validate(src, dst, out, stream=None) -> None:
+    """Enqueue copy src -> dst (uint8 tensors, src may be pinned host memory) with validation in one pass.
+
+    out (CUDA int64, 1 element) receives src's first-error offset (-1 if valid).
+    """
+    torch = _torch()
+    if not isinstance(src, torch.Tensor) or src.dtype != torch.uint8 or not src.is_contiguous():
+        raise TypeError("src must be a contiguous uint8 tensor (CUDA or pinned host)")
+    _dev_u8(dst, "dst")
+    if dst.numel() < src.numel():
+        raise ValueError("dst is smaller than src")
+    check(load().utf8v_copy_validate(dst.data_ptr() if dst.numel() else None,
+                                     src.data_ptr() if src.numel() else None, src.numel(), out.data_ptr(),
+                                     _stream_handle(stream)), "utf8v_copy_validate")
 
 
 ERROR_CLASSES = {0: "valid", 1: "five_plus_byte", 2: "too_short", 3: "too_long", 4: "overlong",

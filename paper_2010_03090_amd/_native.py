@@ -68,6 +68,7 @@ SIGNATURES = {
     "utf8v_server_stats": (_i32, [_vp, _vp]),
     "utf8v_server_destroy": (_i32, [_vp]),
     "utf8v_clock_ns": (_i64, []),
+    "utf8v_copy_validate": (_i32, [_vp, _vp, _sz, _vp, _vp]),
     "utf8v_error_class": (_i32, [_vp, _sz, _vp, _vp, _vp]),
     "utf8v_error_classes": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "utf8v_stream_create": (_i32, [ctypes.POINTER(_vp), _vp]),

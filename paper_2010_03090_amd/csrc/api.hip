@@ -365,6 +365,31 @@ int utf8v_stream_destroy(utf8v_stream* s) {
   return set_status(UTF8V_OK);
 }
 
+int utf8v_copy_validate(uint8_t* dst, const uint8_t* src, size_t len, int64_t* dev_first_err, void* stream) {
+  if (!dev_first_err || ((src == nullptr || dst == nullptr) && len != 0)) return set_status(UTF8V_EINVAL);
+  if (len != 0 && ((reinterpret_cast<uintptr_t>(dst) ^ reinterpret_cast<uintptr_t>(src)) & 15) != 0)
+    return set_status(UTF8V_EINVAL);
+  if (len != 0 && reinterpret_cast<uintptr_t>(dst) < reinterpret_cast<uintptr_t>(src) + len &&
+      reinterpret_cast<uintptr_t>(src) < reinterpret_cast<uintptr_t>(dst) + len)
+    return set_status(UTF8V_EINVAL);
+  for (const void* p : {(const void*)dst, (const void*)src, (const void*)dev_first_err}) {
+    if (p == nullptr) continue;
+    int rc = check_device_ptr(p);
+    if (rc) return rc;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Workspace* ws = nullptr;
+  int rc = workspace(st, &ws);
+  if (rc) return rc;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const int cus = num_cus_of(dev);
+  hipError_t e = utf8v::launch_copy_validate(dst, src, (uint64_t)len, ws->state, dev_first_err, tune_single(),
+                                             cus > 0 ? cus : 1, st);
+  if (e != hipSuccess) return hip_fail(e);
+  return set_status(UTF8V_OK);
+}
+
 int utf8v_error_class(const uint8_t* buf, size_t len, const int64_t* dev_first_err, uint8_t* dev_class,
                       void* stream) {
   if ((buf == nullptr && len != 0) || !dev_first_err || !dev_class) return set_status(UTF8V_EINVAL);

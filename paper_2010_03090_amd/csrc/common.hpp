@@ -45,6 +45,12 @@ hipError_t launch_single(const uint8_t* buf, uint64_t n, unsigned long long* sta
 hipError_t launch_stream_chunk(const uint8_t* buf, uint64_t n, unsigned long long* state, int64_t* out,
                                unsigned long long* hist, int64_t base, bool end_check, bool keep_first,
                                const TuneSingle& cfg, int num_cus, hipStream_t st);
+// Copy src to dst (same address modulo 16, no overlap) and validate it in the same pass.
+hipError_t launch_copy_validate(uint8_t* dst, const uint8_t* src, uint64_t n, unsigned long long* state,
+                                int64_t* out, const TuneSingle& cfg, int num_cus, hipStream_t st);
+hipError_t launch_single_any(const uint8_t* buf, uint8_t* dst, uint64_t n, unsigned long long* state, int64_t* out,
+                             unsigned long long* hist, int64_t base, bool end_check, bool keep_first,
+                             const TuneSingle& cfg, int num_cus, hipStream_t st);
 BatchArgs batch_args(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* flags, int64_t* first_err,
                      unsigned long long* slot);
 hipError_t launch_batch(const BatchArgs& a, const TuneBatch& cfg, int num_cus, hipStream_t st);

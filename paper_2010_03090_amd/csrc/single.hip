@@ -44,6 +44,7 @@ struct SingleArgs {
   int64_t base;               // stream position of byte 0 (offsets written are stream positions)
   int end_check;              // apply the section 6.3 end check at position n (else positions >= n do not exist)
   int keep_first;             // leave *out alone if it already holds an error; write no -1
+  uint8_t* dst;               // copy the buffer here while validating it (the copying kernel only)
 };
 
 // Byte at position p of a buffer whose history (positions -8..-1) is h; zero elsewhere.
@@ -81,6 +82,17 @@ __device__ __forceinline__ void load_tile(u32x4 (&x)[U], const uint8_t* __restri
   for (int u = 0; u < U; ++u) {
     const uint64_t pos = base + (uint64_t)u * 1024 + (uint64_t)lane * 16;
     x[u] = (FULL || pos < i1) ? load16(buf + pos) : u32x4{0, 0, 0, 0};
+  }
+}
+
+// Streaming 16-byte stores of a tile (the copying kernel): the same positions in dst.
+template <int U, bool FULL>
+__device__ __forceinline__ void store_tile(const u32x4 (&x)[U], uint8_t* __restrict__ dst, uint64_t base,
+                                           uint64_t i1, int lane) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint64_t pos = base + (uint64_t)u * 1024 + (uint64_t)lane * 16;
+    if (FULL || pos < i1) __builtin_nontemporal_store(x[u], reinterpret_cast<u32x4*>(dst + pos));
   }
 }
 
@@ -219,7 +231,7 @@ __device__ __forceinline__ uint64_t arrive(unsigned long long* w, uint64_t mine)
 // others exit without waiting): on one of up to kStateGroups group words
 // (workgroup index modulo the group count), and the last workgroup of a group
 // reports the group on the top word, so no word sees many arrivals.
-template <int U, bool ASCII>
+template <int U, bool ASCII, bool COPY>
 __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
   __shared__ unsigned long long blk_min;  // least detection of the workgroup's waves so far
   __shared__ unsigned blk_done;           // waves of the workgroup that have finished
@@ -233,6 +245,11 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
   }
   __syncthreads();
   uint64_t edge = kNone;  // the last wave (usually the one with the fewest tiles) also checks the edges
+  if (COPY && wave == waves - 1) {  // and copies the bytes outside the interior
+    const int64_t n = (int64_t)a.n, i0 = (int64_t)a.i0, i1 = (int64_t)a.i1;
+    if (lane < 16 && lane < i0 && lane < n) a.dst[lane] = a.buf[lane];
+    if (lane >= 16 && lane < 32 && i1 + lane - 16 < n && i1 >= i0) a.dst[i1 + lane - 16] = a.buf[i1 + lane - 16];
+  }
   if (wave == waves - 1 && lane == 0) edge = edge_detection(a);
   uint64_t t = wave * a.tiles_per_wave;
   const uint64_t t_end = t + a.tiles_per_wave < a.tiles ? t + a.tiles_per_wave : a.tiles;
@@ -248,11 +265,14 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
       load_tile<U, true>(xa, a.buf, a.i0 + t * W, a.i1, lane);
       for (; t + 1 < t_full; t += 2) {
         load_tile<U, true>(xb, a.buf, a.i0 + (t + 1) * W, a.i1, lane);
+        if (COPY) store_tile<U, true>(xa, a.dst, a.i0 + t * W, a.i1, lane);
         single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii_skip);
         if (t + 2 < t_full) load_tile<U, true>(xa, a.buf, a.i0 + (t + 2) * W, a.i1, lane);
+        if (COPY) store_tile<U, true>(xb, a.dst, a.i0 + (t + 1) * W, a.i1, lane);
         single_tile<U, ASCII, true>(xb, a.i0 + (t + 1) * W, a.i1, lane, carry, dmin, ascii_skip);
       }
       if (t < t_full) {
+        if (COPY) store_tile<U, true>(xa, a.dst, a.i0 + t * W, a.i1, lane);
         single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii_skip);
         ++t;
       }
@@ -260,6 +280,7 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
     if (t < t_end) {
       u32x4 x[U];
       load_tile<U, false>(x, a.buf, a.i0 + t * W, a.i1, lane);
+      if (COPY) store_tile<U, false>(x, a.dst, a.i0 + t * W, a.i1, lane);
       single_tile<U, ASCII, false>(x, a.i0 + t * W, a.i1, lane, carry, dmin, ascii_skip);
     }
   }
@@ -306,7 +327,10 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
 
 template <int U, bool ASCII>
 static hipError_t launch_single_t(const SingleArgs& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((single_main<U, ASCII>), dim3(grid), dim3(256), 0, st, a);
+  if (a.dst)
+    hipLaunchKernelGGL((single_main<U, ASCII, true>), dim3(grid), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((single_main<U, ASCII, false>), dim3(grid), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -318,6 +342,18 @@ hipError_t launch_single(const uint8_t* buf, uint64_t n, unsigned long long* sta
 hipError_t launch_stream_chunk(const uint8_t* buf, uint64_t n, unsigned long long* state, int64_t* out,
                                unsigned long long* hist, int64_t base, bool end_check, bool keep_first,
                                const TuneSingle& cfg, int num_cus, hipStream_t st) {
+  return launch_single_any(buf, nullptr, n, state, out, hist, base, end_check, keep_first, cfg, num_cus, st);
+}
+
+hipError_t launch_copy_validate(uint8_t* dst, const uint8_t* src, uint64_t n, unsigned long long* state,
+                                int64_t* out, const TuneSingle& cfg, int num_cus, hipStream_t st) {
+  if (((reinterpret_cast<uintptr_t>(dst) ^ reinterpret_cast<uintptr_t>(src)) & 15) != 0) return hipErrorInvalidValue;
+  return launch_single_any(src, dst, n, state, out, nullptr, 0, true, false, cfg, num_cus, st);
+}
+
+hipError_t launch_single_any(const uint8_t* buf, uint8_t* dst, uint64_t n, unsigned long long* state, int64_t* out,
+                             unsigned long long* hist, int64_t base, bool end_check, bool keep_first,
+                             const TuneSingle& cfg, int num_cus, hipStream_t st) {
   if (n >= kPosNone) return hipErrorInvalidValue;
   const uint64_t mis = (uint64_t)(reinterpret_cast<uintptr_t>(buf) & 15);
   const uint64_t i0 = mis ? 16 - mis : 0;
@@ -328,6 +364,7 @@ hipError_t launch_stream_chunk(const uint8_t* buf, uint64_t n, unsigned long lon
   SingleArgs a;
   a.buf = buf; a.n = n; a.i0 = i0; a.i1 = i1; a.state = state; a.out = out;
   a.hist = hist; a.base = base; a.end_check = end_check ? 1 : 0; a.keep_first = keep_first ? 1 : 0;
+  a.dst = dst;
   a.tiles = i1 > i0 ? (i1 - i0 + W - 1) / W : 0;
   const uint64_t max_waves = (uint64_t)num_cus * (uint64_t)cfg.waves_per_cu;
   a.tiles_per_wave = (a.tiles + max_waves - 1) / max_waves;

@@ -483,3 +483,36 @@ def test_error_classes_batch_exhaustive_and_mixed(u8):
             assert set(np.unique(c_o).tolist()) == {0, 1, 2, 3, 4, 6}
         if i == 1:   # the injected error kinds reach every class but 5+ byte leads alone
             assert {2, 3, 4, 5, 6} <= set(np.unique(c_o).tolist())
+
+
+def test_copy_validate(u8):
+    """One pass copies and validates: dst equals src, offsets equal the oracle's (device and pinned host src)."""
+    rng = np.random.default_rng(29)
+    out = torch.empty(1, dtype=torch.int64, device="cuda")
+    sizes = [0, 1, 3, 15, 16, 17, 63, 4095, 4097, 65_537, 1_000_003]
+    for i, n in enumerate(sizes):
+        b = synth.text(n, ["mixed", "cjk", "emoji", "random"][i % 4], 50 + i)
+        if n > 8 and i % 2:
+            synth.inject(b, int(rng.integers(0, n)), i % 7, i)
+        exp = oracle.first_error(b)
+        for host_src in (False, True):
+            for off in (0, 5, 15):
+                say(f"case: copy_validate n {n} host {host_src} offset {off}")
+                base = torch.from_numpy(np.concatenate([np.zeros(off, np.uint8), b, np.zeros(7, np.uint8)]))
+                src = (base.pin_memory() if host_src else base.cuda())[off:off + n]
+                dbuf = torch.full((n + 64,), 0xAB, dtype=torch.uint8, device="cuda")
+                dst = dbuf[off + 16:off + 16 + n]
+                u8.copy_validate(src, dst, out)
+                torch.cuda.synchronize()
+                assert int(out[0]) == exp, (n, host_src, off)
+                d = dbuf.cpu().numpy()
+                assert np.array_equal(d[off + 16:off + 16 + n], b)
+                assert (d[:off + 16] == 0xAB).all() and (d[off + 16 + n:] == 0xAB).all()   # nothing outside dst
+
+
+def test_copy_validate_rejects_misaligned_or_overlapping(u8):
+    lib = u8.load()
+    t = torch.zeros(4096, dtype=torch.uint8, device="cuda")
+    out = torch.empty(1, dtype=torch.int64, device="cuda")
+    assert lib.utf8v_copy_validate(t.data_ptr() + 1, t.data_ptr() + 2048, 100, out.data_ptr(), None) == -1
+    assert lib.utf8v_copy_validate(t.data_ptr() + 16, t.data_ptr(), 100, out.data_ptr(), None) == -1
