@@ -263,25 +263,29 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
   for (; t < t_end; ++t) {
     const int64_t ts = c0 + t * kTile;
     const int64_t te = ts + kTile;
-    // 1. string-start mask of positions [ts-4, te) in LDS; boundaries [k0, k1) of the window
-#pragma unroll
-    for (int u = 0; u < kU; ++u) reinterpret_cast<u32x4*>(smask + kMaskPad)[u * 64 + lane] = u32x4{0, 0, 0, 0};
-    if (lane0) *reinterpret_cast<u32x4*>(smask) = u32x4{0, 0, 0, 0};
-    __syncthreads();
+    // 1. string-start mask of positions [ts-4, te) in LDS; boundaries [k0, k1) of the window.
+    // A tile inside one string (the window's first boundary lies past it) needs neither.
+    const bool plain = uniform(v) >= te;
     int64_t cnt = 0, cnt_next = 0, cnt_before = 0;
-    for (;;) {
-      const bool in = v < te;
-      if (in) {
-        smask[v - ts + kMaskPad] = 0xFF;
-        if (cnt + lane < kOffCap) soff[cnt + lane] = v;
+    if (!plain) {
+#pragma unroll
+      for (int u = 0; u < kU; ++u) reinterpret_cast<u32x4*>(smask + kMaskPad)[u * 64 + lane] = u32x4{0, 0, 0, 0};
+      if (lane0) *reinterpret_cast<u32x4*>(smask) = u32x4{0, 0, 0, 0};
+      __syncthreads();
+      for (;;) {
+        const bool in = v < te;
+        if (in) {
+          smask[v - ts + kMaskPad] = 0xFF;
+          if (cnt + lane < kOffCap) soff[cnt + lane] = v;
+        }
+        const int c = __popcll(__ballot(in));
+        cnt_next += __popcll(__ballot(v < te - 4));
+        cnt_before += __popcll(__ballot(v < ts));
+        cnt += c;
+        if (c < 64) break;
+        const int64_t idx = k0 + cnt + lane;
+        v = idx <= n ? offsets[idx] : INT64_MAX;
       }
-      const int c = __popcll(__ballot(in));
-      cnt_next += __popcll(__ballot(v < te - 4));
-      cnt_before += __popcll(__ballot(v < ts));
-      cnt += c;
-      if (c < 64) break;
-      const int64_t idx = k0 + cnt + lane;
-      v = idx <= n ? offsets[idx] : INT64_MAX;
     }
     const int64_t k1 = uniform(k0 + cnt);          // boundaries in [ts-4, te): [k0, k1)
     const int64_t kb = uniform(k0 + cnt_before);   // boundaries in [ts, te): [kb, k1)
@@ -290,7 +294,7 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     const int64_t k0n = k0 + cnt_next;
     if (t + 1 < t_end) {
       batch_load(nx, data, te, lo, hi, lane);
-      v = k0n + lane <= n ? offsets[k0n + lane] : INT64_MAX;
+      if (!plain) v = k0n + lane <= n ? offsets[k0n + lane] : INT64_MAX;  // (plain: the same window)
     }
     __syncthreads();
     if (open_k == -2) {  // first tile of the wave
@@ -320,14 +324,23 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     if (run) {
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
+        uint32_t acc = 0, tail = 0;
+        if (plain) {
+          acc = chunk_errors(0u, x[u].x, x[u].y, x[u].z, x[u].w, prev[u]);
+          bad |= acc ? (1u << u) : 0u;
+          continue;
+        }
         const u32x4 s4 = reinterpret_cast<const u32x4*>(smask + kMaskPad)[u * 64 + lane];
         const uint32_t sp = *reinterpret_cast<const uint32_t*>(smask + kMaskPad + u * 1024 + lane * 16 - 4);
-        uint32_t acc = 0, tail = 0;
-        MaskedCarry c = masked_halo(prev[u], sp);
-        masked_next(x[u].x, prev[u], s4.x, sp, c, acc, tail);
-        masked_next(x[u].y, x[u].x, s4.y, s4.x, c, acc, tail);
-        masked_next(x[u].z, x[u].y, s4.z, s4.y, c, acc, tail);
-        masked_next(x[u].w, x[u].z, s4.w, s4.z, c, acc, tail);
+        if (__any((s4.x | s4.y | s4.z | s4.w | sp) != 0u)) {
+          MaskedCarry c = masked_halo(prev[u], sp);
+          masked_next(x[u].x, prev[u], s4.x, sp, c, acc, tail);
+          masked_next(x[u].y, x[u].x, s4.y, s4.x, c, acc, tail);
+          masked_next(x[u].z, x[u].y, s4.z, s4.y, c, acc, tail);
+          masked_next(x[u].w, x[u].z, s4.w, s4.z, c, acc, tail);
+        } else {  // no string starts in the slab or the 4 bytes before it: the plain checks
+          acc = chunk_errors(0u, x[u].x, x[u].y, x[u].z, x[u].w, prev[u]);
+        }
         bad |= (acc | tail) ? (1u << u) : 0u;
       }
     }
@@ -336,8 +349,9 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     if (__builtin_expect(bad != 0, 0)) {
       for (int u = 0; u < kU; ++u) {
         if (!((bad >> u) & 1)) continue;
-        const u32x4 s4 = reinterpret_cast<const u32x4*>(smask + kMaskPad)[u * 64 + lane];
-        const uint32_t sp = *reinterpret_cast<const uint32_t*>(smask + kMaskPad + u * 1024 + lane * 16 - 4);
+        const u32x4 s4 = plain ? u32x4{0, 0, 0, 0} : reinterpret_cast<const u32x4*>(smask + kMaskPad)[u * 64 + lane];
+        const uint32_t sp =
+            plain ? 0u : *reinterpret_cast<const uint32_t*>(smask + kMaskPad + u * 1024 + lane * 16 - 4);
         const uint32_t xs[5] = {prev[u], x[u].x, x[u].y, x[u].z, x[u].w};
         const uint32_t ss[5] = {sp, s4.x, s4.y, s4.z, s4.w};
         MaskedCarry c = masked_halo(prev[u], sp);
