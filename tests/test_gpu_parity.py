@@ -516,3 +516,58 @@ def test_copy_validate_rejects_misaligned_or_overlapping(u8):
     out = torch.empty(1, dtype=torch.int64, device="cuda")
     assert lib.utf8v_copy_validate(t.data_ptr() + 1, t.data_ptr() + 2048, 100, out.data_ptr(), None) == -1
     assert lib.utf8v_copy_validate(t.data_ptr() + 16, t.data_ptr(), 100, out.data_ptr(), None) == -1
+
+
+def test_async_calls_captured_in_a_torch_graph(u8):
+    """validate_async / validate_batch_async captured in a HIP graph (torch.cuda.CUDAGraph), replayed
+    several times with eager work and synchronizations between, each replay checked."""
+    b = synth.text(3_000_017, "mixed", 60)
+    synth.inject(b, 2_000_000, "surrogate", 1)
+    exp = oracle.first_error(b)
+    data, offsets, _ = synth.lognormal_batch(50_000, 61)
+    f_o, e_o = oracle.first_error_batch(data, offsets)
+    tb, td, to = dev(b), dev(data), dev(offsets)
+    out = torch.full((1,), -9, dtype=torch.int64, device="cuda")
+    flags = torch.empty(e_o.size, dtype=torch.uint8, device="cuda")
+    ferr = torch.empty(e_o.size, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):   # first calls on this stream create its workspace outside the capture
+        u8.validate_async(tb, out)
+        u8.validate_batch_async(td, to, flags, ferr)
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        u8.validate_async(tb, out)
+        u8.validate_batch_async(td, to, flags, ferr)
+    for rep in range(4):
+        say(f"case: torch graph replay {rep}")
+        out.fill_(-9)
+        ferr.fill_(-9)
+        flags.fill_(9)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(out[0]) == exp
+        assert np.array_equal(ferr.cpu().numpy(), e_o) and np.array_equal(flags.cpu().numpy(), f_o)
+        assert u8.first_error(tb) == exp          # eager work between replays
+
+
+def test_batch_many_empty_strings(u8):
+    """Runs of empty strings (many boundaries at one position) between non-empty ones."""
+    rng = np.random.default_rng(62)
+    lens = np.zeros(200_000, np.int64)
+    idx = rng.choice(lens.size, 3000, replace=False)
+    lens[idx] = rng.integers(1, 3000, idx.size)
+    for err in (0.0, 0.3):
+        say(f"case: many empty strings, err {err}")
+        data, offsets, expected = synth.batch_from_lengths(lens, "mixed", 63, err_frac=err)
+        f_o, e_o = oracle.first_error_batch(data, offsets)
+        flags, ferr = u8.validate_batch(dev(data), dev(offsets))
+        torch.cuda.synchronize()
+        assert np.array_equal(ferr.cpu().numpy(), e_o)
+        assert np.array_equal(flags.cpu().numpy(), f_o)
+    lens = np.zeros(1000, np.int64)                # only empty strings
+    data, offsets, _ = synth.batch_from_lengths(lens, "mixed", 64, base=5)
+    flags, ferr = u8.validate_batch(dev(np.zeros(8, np.uint8)), dev(offsets))
+    torch.cuda.synchronize()
+    assert (ferr.cpu().numpy() == -1).all() and (flags.cpu().numpy() == 1).all()
