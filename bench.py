@@ -120,6 +120,7 @@ def main():
     # ---- CPU oracle on a bounded sample (1 core, as the paper's single thread) -----------------
     if not args.no_cpu and "random" in host and len(host) > 1:
         result["cpu_baseline"] = cpu_baseline(host, args.size, args.cpu_seconds)
+        result["host_simd_lookup"] = host_simd_baseline(host, args.size)
     print(json.dumps(result), flush=True)
 
 
@@ -647,6 +648,28 @@ def cpu_baseline(host, n, seconds):
             "sample": f"branchy oracle on 1 thread over the first ~{mib:.0f} MiB of each valid variant buffer "
                       f"(ascii, latin, cjk, emoji; 16 MiB segments, ~{budget:.1f} s each)",
             "per_variant_GBps": per_variant, "host_cpu": cpu, "host_threads": os.cpu_count()}
+
+
+def host_simd_baseline(host, n):
+    """The section 6 lookup algorithm with AVX2 on the host (the paper's own method on a CPU),
+    1 thread and all threads, on the valid variant buffers.  A reference point only."""
+    from paper_2010_03090_amd import baselines
+    if not baselines.supported():
+        return None
+    threads = min(os.cpu_count() or 1, 64)
+    row = {"unit": "GB/s", "threads_all": threads}
+    for label, nt in (("one_thread", 1), ("all_threads", threads)):
+        per = {}
+        for name in (k for k in host if k != "random"):
+            h = host[name][: n if nt > 1 else min(n, 256 << 20)]
+            baselines.is_valid(h[: 1 << 20], nt)
+            t0 = time.perf_counter()
+            ok = baselines.is_valid(h, nt)
+            per[name] = round(h.size / (time.perf_counter() - t0) / 1e9, 2)
+            if not ok:
+                raise SystemExit(f"host lookup baseline rejected valid {name}")
+        row[label] = per
+    return row
 
 
 if __name__ == "__main__":
