@@ -66,6 +66,7 @@ def parse():
     ap.add_argument("--no-heavy", action="store_true", help="skip the heavy-tail batches")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--no-copy", action="store_true", help="skip the fused copy + validate part")
+    ap.add_argument("--no-latency", action="store_true", help="skip the 1 MiB latency part")
     ap.add_argument("--serve-loads", default="10000,50000,200000", help="offered loads, requests/s")
     ap.add_argument("--serve-requests", type=int, default=100_000, help="measured requests per load")
     ap.add_argument("--serve-baseline-requests", type=int, default=20_000,
@@ -104,6 +105,10 @@ def main():
     # ---- batched: 1M log-normal strings vs one launch per string ------------------------------
     if not args.no_batch:
         result["batched"] = bench_batch(u8, lib, synth, torch, dev, stream, sh, args)
+
+    # ---- latency of one 1 MiB buffer (the mixed-text correctness workload) ----------------------
+    if not args.no_latency:
+        result["latency_1mib"] = bench_latency(u8, lib, synth, torch, dev, stream, sh)
 
     # ---- fused copy + validate (device to device, pinned host to device) ----------------------
     if not args.no_copy:
@@ -448,6 +453,41 @@ def bench_graph(u8, lib, torch, td, to, flags, ferr, nstr, offsets, expected, st
                 raise SystemExit(f"wrong {name} small-batch result")
         out[f"n{n}"] = row
     return out
+
+
+def bench_latency(u8, lib, synth, torch, dev, stream, sh):
+    """1 MiB of mixed text (and 64 corrupted copies): host-measured latency of a synchronous
+    validate (launch, kernel, result copy, wait), and pipelined launches per second."""
+    import ctypes
+    clean, copies = synth.single_buffer_with_errors(1 << 20, "mixed", 0, 64)
+    bufs = [torch.from_numpy(clean).to(dev)] + [torch.from_numpy(c).to(dev) for c, _, _ in copies]
+    expect = [-1] + [int(s) for _, s, _ in copies]
+    out = ctypes.c_int64(0)
+    lat = []
+    for rep in range(30):
+        for t, e in zip(bufs, expect):
+            t0 = time.perf_counter()
+            lib.utf8v_validate_ex(t.data_ptr(), t.numel(), ctypes.byref(out), sh)
+            lat.append(time.perf_counter() - t0)
+            if out.value != e:
+                raise SystemExit("wrong 1 MiB result")
+    lat = np.array(lat[len(bufs):]) * 1e6
+    res = torch.empty(len(bufs), dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 20
+    for _ in range(reps):
+        for i, t in enumerate(bufs):
+            lib.utf8v_validate_async(t.data_ptr(), t.numel(), res.data_ptr() + 8 * i, sh)
+    torch.cuda.synchronize()
+    per = (time.perf_counter() - t0) / (reps * len(bufs))
+    if res.cpu().numpy().tolist() != expect:
+        raise SystemExit("wrong pipelined 1 MiB result")
+    return {"workload": "1 MiB mixed text + 64 copies with one injected error each",
+            "sync_latency_us_p50": round(float(np.percentile(lat, 50)), 1),
+            "sync_latency_us_p99": round(float(np.percentile(lat, 99)), 1),
+            "pipelined_us_per_buffer": round(per * 1e6, 2),
+            "pipelined_GBps_cache_resident": round((1 << 20) / per / 1e9, 1)}
 
 
 def bench_copy(u8, synth, torch, dev, stream, args):
