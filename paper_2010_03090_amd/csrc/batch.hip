@@ -403,6 +403,13 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     }
     for (int64_t j0 = kb; j0 < k1 - 1; j0 += 64) {  // strings that start and end in the tile
       const int64_t k = j0 + lane;
+      if (!tile_bad) {  // no error anywhere in the tile: every such string is valid
+        if (k < k1 - 1) {
+          a.flags[k] = 1;
+          a.first_err[k] = -1;
+        }
+        continue;
+      }
       if (k < k1 - 1) {
         const int64_t st = boundary(k, offsets, k0, k1, soff), en = boundary(k + 1, offsets, k0, k1, soff);
         int64_t d = kNoneRel;
