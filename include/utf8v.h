@@ -52,8 +52,9 @@ extern "C" {
 
 /*
  * utf8_validate -- true iff buf[0..len) is valid UTF-8 (section 6 lookup
- * algorithm over one buffer).  buf may be NULL iff len == 0.  Synchronous on
- * the default stream.  On misuse it returns false and sets utf8v_last_status().
+ * algorithm over one buffer).  buf may be NULL iff len == 0; len < 2^40.
+ * Synchronous on the default stream.  On misuse it returns false and sets
+ * utf8v_last_status().
  */
 bool utf8_validate(const uint8_t *buf, size_t len);
 
@@ -159,7 +160,8 @@ int utf8v_error_classes(const uint8_t *data, const int64_t *offsets, int64_t n, 
  * character, into empty or one-byte chunks -- gives the same result as
  * validating them whole.  The state (first-error offset and the last 8 bytes)
  * lives on the device, so updates are asynchronous and ordered by the HIP
- * stream they are enqueued on; use one HIP stream per utf8v_stream.
+ * stream they are enqueued on; use one HIP stream per utf8v_stream and call it
+ * from one host thread at a time.  Streams are limited to 2^40 - 1 bytes.
  */
 typedef struct utf8v_stream utf8v_stream;
 

@@ -150,7 +150,7 @@ utf8v::TuneBatch tune_batch() {
 }
 
 int enqueue_single(const uint8_t* buf, size_t len, int64_t* dev_out, hipStream_t st, Workspace** ws_out) {
-  if (buf == nullptr && len != 0) return set_status(UTF8V_EINVAL);
+  if ((buf == nullptr && len != 0) || (uint64_t)len >= utf8v::kPosNone) return set_status(UTF8V_EINVAL);
   if (len != 0) {
     int rc = check_device_ptr(buf);
     if (rc) return rc;
@@ -175,7 +175,11 @@ extern "C" {
 int utf8v_validate_ex(const uint8_t* buf, size_t len, int64_t* first_err, void* stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Workspace* ws = nullptr;
-  int rc = enqueue_single(buf, len, nullptr, st, &ws);
+  int rc = workspace(st, &ws);
+  if (rc) return rc;
+  // the result slot and its host copy are the workspace's: one synchronous call per stream at a time
+  std::lock_guard<std::mutex> lk(ws->mu);
+  rc = enqueue_single(buf, len, nullptr, st, &ws);
   if (rc) return rc;
   hipError_t e = hipMemcpyAsync(ws->host, ws->result, sizeof(int64_t), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -308,7 +312,9 @@ int utf8v_stream_create(utf8v_stream** out, void* stream) {
 }
 
 int utf8v_stream_update(utf8v_stream* s, const uint8_t* chunk, size_t len, void* stream) {
-  if (!s || (chunk == nullptr && len != 0)) return set_status(UTF8V_EINVAL);
+  if (!s || (chunk == nullptr && len != 0) || (uint64_t)len >= utf8v::kPosNone ||
+      (uint64_t)s->total + (uint64_t)len >= utf8v::kPosNone)
+    return set_status(UTF8V_EINVAL);
   if (len == 0) return set_status(UTF8V_OK);
   int rc = check_device_ptr(chunk);
   if (rc) return rc;
@@ -437,6 +443,7 @@ int utf8v_check_offsets(const int64_t* offsets, int64_t n, void* stream) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   const int cus = num_cus_of(dev);
+  std::lock_guard<std::mutex> lk(ws->mu);  // the flag and its host copy are the workspace's
   hipError_t e = hipMemsetAsync(ws->flag, 0, sizeof(int), st);
   if (e == hipSuccess) e = utf8v::launch_offsets_check(offsets, n, ws->flag, cus > 0 ? cus : 1, st);
   if (e == hipSuccess) e = hipMemcpyAsync(ws->host, ws->flag, sizeof(int), hipMemcpyDeviceToHost, st);

@@ -571,3 +571,32 @@ def test_batch_many_empty_strings(u8):
     flags, ferr = u8.validate_batch(dev(np.zeros(8, np.uint8)), dev(offsets))
     torch.cuda.synchronize()
     assert (ferr.cpu().numpy() == -1).all() and (flags.cpu().numpy() == 1).all()
+
+
+def test_sync_calls_from_many_threads_on_one_stream(u8):
+    """Synchronous validations issued concurrently from host threads on the same stream each get their own result."""
+    import threading
+    bufs = []
+    for i in range(8):
+        b = synth.text(400_000 + 4099 * i, "mixed", 70 + i)
+        if i % 2:
+            synth.inject(b, 100_000 * (i % 4) + 77, i % 7, i)
+        bufs.append((dev(b), oracle.first_error(b)))
+    errors = []
+
+    def worker(k):
+        try:
+            for rep in range(25):
+                t, exp = bufs[(k + rep) % len(bufs)]
+                got = u8.first_error(t, stream=torch.cuda.default_stream())
+                if got != exp:
+                    errors.append((k, rep, got, exp))
+        except Exception as e:  # noqa: BLE001
+            errors.append(repr(e))
+    say("case: 6 host threads, one stream")
+    th = [threading.Thread(target=worker, args=(k,)) for k in range(6)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors[:5]
