@@ -173,6 +173,7 @@ int enqueue_single(const uint8_t* buf, size_t len, int64_t* dev_out, hipStream_t
 extern "C" {
 
 int utf8v_validate_ex(const uint8_t* buf, size_t len, int64_t* first_err, void* stream) {
+  if ((buf == nullptr && len != 0) || (uint64_t)len >= utf8v::kPosNone) return set_status(UTF8V_EINVAL);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Workspace* ws = nullptr;
   int rc = workspace(st, &ws);
