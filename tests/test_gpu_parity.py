@@ -33,7 +33,10 @@ def u8():
 
 
 def dev(a):
-    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    a = np.ascontiguousarray(a)
+    if not a.flags.writeable:
+        a = a.copy()
+    return torch.from_numpy(a).cuda()
 
 
 def test_table9_on_gpu(u8):
