@@ -123,9 +123,4 @@ inline BatchPlan plan_batch(const std::vector<PlanRequest>& reqs, size_t first, 
   return p;
 }
 
-// Ring bytes a batch of these requests needs (upper bound used for admission).
-inline uint64_t batch_footprint(const std::vector<PlanRequest>& reqs, size_t first, size_t count, uint64_t desc_bytes) {
-  return plan_batch(reqs, first, count, desc_bytes).total;
-}
-
 }  // namespace utf8v
