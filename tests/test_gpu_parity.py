@@ -603,3 +603,44 @@ def test_sync_calls_from_many_threads_on_one_stream(u8):
     for t in th:
         t.join()
     assert not errors, errors[:5]
+
+
+def _exhaustive_short_batch():
+    parts, lens = [], []
+    for n in range(1, 4):
+        v = np.arange(256 ** n, dtype=np.uint32)
+        strs = np.stack([(v >> (8 * k)) & 0xFF for k in range(n)], 1).astype(np.uint8)
+        parts.append(strs.reshape(-1))
+        lens += [n] * strs.shape[0]
+    return np.concatenate(parts), np.array(lens, np.int64)
+
+
+def test_batch_exhaustive_short_strings_at_shifted_alignments(u8):
+    """Every string of 1..3 bytes, with the whole batch shifted against 16-byte chunks, 1 KiB slabs
+    and 4 KiB tiles (a prefix of k bytes before offsets[0])."""
+    data, lens = _exhaustive_short_batch()
+    offsets = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    f_o, e_o = oracle.first_error_batch(data, offsets)
+    for k in (1, 2, 3, 13, 15, 16, 17, 1021, 1023, 1025, 4093, 4095, 4097, 4099):
+        say(f"case: exhaustive <= 3 shifted by {k}")
+        shifted = np.concatenate([np.full(k, 0xE2, np.uint8), data])   # a lead byte run before the batch
+        flags, ferr = u8.validate_batch(dev(shifted), dev(offsets + k))
+        torch.cuda.synchronize()
+        assert np.array_equal(ferr.cpu().numpy(), e_o), k
+        assert np.array_equal(flags.cpu().numpy(), f_o), k
+
+
+def test_batch_boundary_alphabet_length_4_and_5(u8):
+    """All strings of length 4 and 5 over the 27 boundary bytes of the byte-range table."""
+    alpha = np.array([0x00, 0x41, 0x7F, 0x80, 0x8F, 0x90, 0x9F, 0xA0, 0xBF, 0xC0, 0xC1, 0xC2, 0xDF, 0xE0,
+                      0xE1, 0xEC, 0xED, 0xEE, 0xEF, 0xF0, 0xF1, 0xF3, 0xF4, 0xF5, 0xF7, 0xF8, 0xFF], np.uint8)
+    for n in (4, 5):
+        say(f"case: boundary alphabet length {n}")
+        idx = np.indices((alpha.size,) * n, dtype=np.int32).reshape(n, -1).T
+        data = alpha[idx].reshape(-1)
+        offsets = np.arange(0, data.size + 1, n, dtype=np.int64)
+        f_o, e_o = oracle.first_error_batch(data, offsets)
+        flags, ferr = u8.validate_batch(dev(data), dev(offsets))
+        torch.cuda.synchronize()
+        assert np.array_equal(ferr.cpu().numpy(), e_o), n
+        assert np.array_equal(flags.cpu().numpy(), f_o), n

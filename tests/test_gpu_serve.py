@@ -113,3 +113,22 @@ def test_serve_replay(sv, mode):
     assert (lat > 0).all() and span > 0
     for k in set(picks.tolist()):
         check(pool[k], expect[k], f"replay mode {mode} request {k}")
+
+
+def test_serve_rejects_oversize_and_bad_requests(sv):
+    """A request larger than the batch limits is rejected with a status; the server keeps serving."""
+    cfg = sv.default_config(max_batch_bytes=1 << 20, max_batch_strings=1 << 12, max_batch_requests=8,
+                            budget_bytes=1 << 24)
+    big_data, big_offsets, _ = synth.batch_from_lengths(np.array([(1 << 20) + 1]), "ascii", 5)
+    many_data, many_offsets, _ = synth.batch_from_lengths(np.ones(1 << 12, np.int64), "ascii", 6)
+    ok_pool, ok_expect = make_pool(sv, [3, 100, 0], 44)
+    with sv.Server(cfg) as srv:
+        for data, offsets in ((big_data, big_offsets), (many_data, many_offsets)):
+            req = sv.Request(data, offsets)
+            with pytest.raises(Exception) as ei:
+                srv.submit(req)
+            assert "invalid argument" in str(ei.value)
+        for r, e in zip(ok_pool, ok_expect):
+            r.reset()
+            srv.wait(srv.submit(r))
+            check(r, e, "after rejections")
