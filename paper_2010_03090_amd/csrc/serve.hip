@@ -6,7 +6,8 @@
 // batch slot is free, so requests that arrive while others are on the GPU join
 // the next batch and batches overlap on alternating streams.  Per batch, on its
 // stream:
-//   1. the descriptor table (and its lookup tables) is copied to the ring;
+//   1. the descriptor table (and its lookup tables) is copied to the ring, or, for a
+//      small batch, passed in the kernel arguments;
 //   2. serve_gather reads the payloads and offsets straight from pinned host
 //      memory into the ring, rebasing the offsets so the requests form one CSR
 //      batch (a padding string separates consecutive requests);
@@ -21,6 +22,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstring>
 #include <chrono>
 #include <deque>
 #include <memory>
@@ -50,25 +52,48 @@ struct ServeDesc {
 constexpr int kGatherChunk = 4096;  // payload bytes per gather workgroup (16 per thread)
 constexpr int kStringBlock = 256;   // strings per offsets / scatter workgroup
 
-// Payload chunks first, then offset blocks.  chunk_req[c] / block_req[b] name the
-// first request overlapping payload chunk c / string block b.
-__global__ __launch_bounds__(256) void serve_gather(const ServeDesc* __restrict__ d, int nreq,
-                                                    const int32_t* __restrict__ chunk_req,
-                                                    const int32_t* __restrict__ block_req, int64_t chunks,
-                                                    uint8_t* __restrict__ data, int64_t data_end,
-                                                    int64_t* __restrict__ offs, int64_t strings) {
+// The batch's descriptor table and its two lookup tables: chunk_req[c] / block_req[b]
+// name the first request overlapping payload chunk c / string block b.  Either in the
+// ring (copied before the gather) or, for small batches, in the kernel arguments.
+struct RingTables {
+  const ServeDesc* d;
+  const int32_t* chunk_req;
+  const int32_t* block_req;
+  __device__ __forceinline__ const ServeDesc& desc(int r) const { return d[r]; }
+  __device__ __forceinline__ int chunk(int64_t c) const { return chunk_req[c]; }
+  __device__ __forceinline__ int block(int64_t b) const { return block_req[b]; }
+};
+
+constexpr int kInlineReqs = 16;      // small-batch limits: the tables fit the kernel arguments
+constexpr int kInlineChunks = 320;
+constexpr int kInlineBlocks = 384;
+
+struct InlineTables {
+  ServeDesc d[kInlineReqs];
+  int32_t chunk_req[kInlineChunks];
+  int32_t block_req[kInlineBlocks];
+  __device__ __forceinline__ const ServeDesc& desc(int r) const { return d[r]; }
+  __device__ __forceinline__ int chunk(int64_t c) const { return chunk_req[c]; }
+  __device__ __forceinline__ int block(int64_t b) const { return block_req[b]; }
+};
+
+// Payload chunks first, then offset blocks.
+template <class T>
+__global__ __launch_bounds__(256) void serve_gather(T t, int nreq, int64_t chunks, uint8_t* __restrict__ data,
+                                                    int64_t data_end, int64_t* __restrict__ offs, int64_t strings) {
   const int64_t b = blockIdx.x;
   if (b < chunks) {
     const int64_t p = b * kGatherChunk + threadIdx.x * 16;  // this thread's 16-byte word of the data region
     if (p >= data_end) return;
-    for (int r = chunk_req[b]; r < nreq && d[r].data_off < p + 16; ++r) {
-      const int64_t s0 = d[r].data_off, s1 = s0 + d[r].bytes;
+    for (int r = t.chunk(b); r < nreq && t.desc(r).data_off < p + 16; ++r) {
+      const ServeDesc& d = t.desc(r);
+      const int64_t s0 = d.data_off, s1 = s0 + d.bytes;
       if (s1 <= p) continue;
       if (s0 <= p && p + 16 <= s1) {  // whole word inside the payload: same alignment on both sides
-        *reinterpret_cast<u32x4*>(data + p) = *reinterpret_cast<const u32x4*>(d[r].src + (p - s0));
+        *reinterpret_cast<u32x4*>(data + p) = *reinterpret_cast<const u32x4*>(d.src + (p - s0));
       } else {
         const int64_t a = p > s0 ? p : s0, e = p + 16 < s1 ? p + 16 : s1;
-        for (int64_t q = a; q < e; ++q) data[q] = d[r].src[q - s0];
+        for (int64_t q = a; q < e; ++q) data[q] = d.src[q - s0];
       }
     }
     return;
@@ -76,27 +101,28 @@ __global__ __launch_bounds__(256) void serve_gather(const ServeDesc* __restrict_
   const int64_t e = (b - chunks) * kStringBlock + threadIdx.x;  // boundary index
   if (e > strings) return;
   if (e == strings) {  // end of the last payload
-    offs[e] = d[nreq - 1].data_off + d[nreq - 1].bytes;
+    offs[e] = t.desc(nreq - 1).data_off + t.desc(nreq - 1).bytes;
     return;
   }
-  int r = block_req[b - chunks];
-  while (r + 1 < nreq && d[r + 1].str_off <= e) ++r;
-  const int64_t k = e - d[r].str_off;  // k <= n: boundary k of request r (k == n: its padding string)
-  offs[e] = k < d[r].n ? d[r].data_off + (d[r].src_off[k] - d[r].src_off[0]) : d[r].data_off + d[r].bytes;
+  int r = t.block(b - chunks);
+  while (r + 1 < nreq && t.desc(r + 1).str_off <= e) ++r;
+  const ServeDesc& d = t.desc(r);
+  const int64_t k = e - d.str_off;  // k <= n: boundary k of request r (k == n: its padding string)
+  offs[e] = k < d.n ? d.data_off + (d.src_off[k] - d.src_off[0]) : d.data_off + d.bytes;
 }
 
-__global__ __launch_bounds__(256) void serve_scatter(const ServeDesc* __restrict__ d, int nreq,
-                                                     const int32_t* __restrict__ block_req,
-                                                     const uint8_t* __restrict__ flags,
+template <class T>
+__global__ __launch_bounds__(256) void serve_scatter(T t, int nreq, const uint8_t* __restrict__ flags,
                                                      const int64_t* __restrict__ errs, int64_t strings) {
   const int64_t e = (int64_t)blockIdx.x * kStringBlock + threadIdx.x;
   if (e >= strings) return;
-  int r = block_req[blockIdx.x];
-  while (r + 1 < nreq && d[r + 1].str_off <= e) ++r;
-  const int64_t k = e - d[r].str_off;
-  if (k < d[r].n) {
-    d[r].dst_flags[k] = flags[e];
-    d[r].dst_err[k] = errs[e];
+  int r = t.block(blockIdx.x);
+  while (r + 1 < nreq && t.desc(r + 1).str_off <= e) ++r;
+  const ServeDesc& d = t.desc(r);
+  const int64_t k = e - d.str_off;
+  if (k < d.n) {
+    d.dst_flags[k] = flags[e];
+    d.dst_err[k] = errs[e];
   }
 }
 
@@ -267,12 +293,28 @@ bool utf8v_server::launch_batch_of(uint64_t first, uint64_t count) {
   uint8_t* flags = base + plan.flags_at;
   int64_t* errs = reinterpret_cast<int64_t*>(base + plan.errs_at);
   const size_t used = (reinterpret_cast<uint8_t*>(block_req) - stg.host) + 4 * blocks;
-  hipError_t e = hipMemcpyAsync(base, stg.host, used, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) {
-    const int64_t grid = (int64_t)chunks + (int64_t)blocks;
-    hipLaunchKernelGGL(serve_gather, dim3((unsigned)grid), dim3(256), 0, st, ddesc, (int)count, dchunk, dblock,
+  const int64_t grid = (int64_t)chunks + (int64_t)blocks;
+  const int64_t sblocks = (plan.strings + kStringBlock - 1) / kStringBlock;
+  // small batches carry the tables in the kernel arguments: no copy ahead of the gather
+  const bool inline_tables = count <= (uint64_t)kInlineReqs && chunks <= (size_t)kInlineChunks &&
+                             blocks <= (size_t)kInlineBlocks;
+  InlineTables it;
+  hipError_t e = hipSuccess;
+  if (inline_tables) {
+    memcpy(it.d, desc, sizeof(ServeDesc) * count);
+    memcpy(it.chunk_req, chunk_req, 4 * chunks);
+    memcpy(it.block_req, block_req, 4 * blocks);
+    hipLaunchKernelGGL(serve_gather<InlineTables>, dim3((unsigned)grid), dim3(256), 0, st, it, (int)count,
                        (int64_t)chunks, data, (int64_t)plan.data_bytes, offs, plan.strings);
     e = hipGetLastError();
+  } else {
+    e = hipMemcpyAsync(base, stg.host, used, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(serve_gather<RingTables>, dim3((unsigned)grid), dim3(256), 0, st,
+                         RingTables{ddesc, dchunk, dblock}, (int)count, (int64_t)chunks, data,
+                         (int64_t)plan.data_bytes, offs, plan.strings);
+      e = hipGetLastError();
+    }
   }
   if (e == hipSuccess) {
     TuneBatch tb;
@@ -281,13 +323,14 @@ bool utf8v_server::launch_batch_of(uint64_t first, uint64_t count) {
     tb.waves_per_cu = c.batch_waves_per_cu;
     e = utf8v::launch_batch(batch_args(data, offs, plan.strings, flags, errs, wslots), tb, cus, st);
   }
-  if (e == hipSuccess) {
-    const int64_t sblocks = (plan.strings + kStringBlock - 1) / kStringBlock;
-    if (sblocks > 0) {
-      hipLaunchKernelGGL(serve_scatter, dim3((unsigned)sblocks), dim3(256), 0, st, ddesc, (int)count, dblock, flags,
-                         errs, plan.strings);
-      e = hipGetLastError();
-    }
+  if (e == hipSuccess && sblocks > 0) {
+    if (inline_tables)
+      hipLaunchKernelGGL(serve_scatter<InlineTables>, dim3((unsigned)sblocks), dim3(256), 0, st, it, (int)count,
+                         flags, errs, plan.strings);
+    else
+      hipLaunchKernelGGL(serve_scatter<RingTables>, dim3((unsigned)sblocks), dim3(256), 0, st,
+                         RingTables{ddesc, dchunk, dblock}, (int)count, flags, errs, plan.strings);
+    e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipEventRecord(stg.ev, st);
   if (e != hipSuccess) {
