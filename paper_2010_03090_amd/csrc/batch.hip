@@ -1,9 +1,8 @@
 // Batched lookup validation of many strings given by CSR offsets, for gfx950.
 //
 // String k is data[offsets[k] .. offsets[k+1]).  Each string is validated as
-// its own stream: the bytes before its start count as zero (section 6, "the
-// previous input is filled with zero") and its end gets the end check of
-// section 6.3.  Results: flags[k] = 1 if valid, first_err[k] = start of the
+// its own stream: the bytes before its start count as zero (as at the start of
+// any input in section 6) and its end gets the end check of section 6.3.  Results: flags[k] = 1 if valid, first_err[k] = start of the
 // first ill-formed character relative to the string start, or -1.
 //
 // One launch does everything.  Work is split by bytes, not by strings: the
@@ -11,22 +10,24 @@
 // grid of one-wave workgroups gives each wave a contiguous run of tiles, so a
 // 64 MiB string and a million 64-byte strings load-balance alike.
 //
-// Per tile the wave writes a byte mask of string starts into LDS (from the
-// offsets falling in the tile), and each lane validates its 16-byte chunks
-// with the bytes of other strings masked to zero:
-//   - the lookup checks of section 6.1-6.2 at position i use prev1/prev2/prev3
-//     only when they belong to the string of position i;
-//   - at every string boundary i, the string that ends there (the one holding
-//     byte i-1) gets the end check of section 6.3 on its own last bytes.
-// Lanes that see an error record, per position, a bit in one of two LDS
-// bitmaps (regular error / end-check error).  Then the wave writes the result
-// of every string whose end lies in the tile: its first detection is the first
-// bit in its own range.  A string that runs across tiles carries its first
-// detection in a wave-uniform register; one that runs across waves gets a
-// partial minimum from every wave it touches, in a workspace slot of the wave
-// holding its start, and the last of those waves to arrive (an arrival count
-// kept in the same 64-bit word) writes its result and resets the slot, so the
-// workspace is clean again when the kernel ends.
+// Per tile the wave first runs the single-buffer checks of section 6 over the tile as
+// plain text, and applies the end check of section 6.3 to the bytes before every
+// string boundary in it.  Where a boundary's end check passes, the string before it
+// ends with a complete character, and then the checks at the boundary and the two
+// positions after it give the same verdict whether or not the bytes of the earlier
+// string are masked to zero; so a tile with neither a plain error nor a failed end
+// check holds only valid strings (the common case, written out directly).  The 1 KiB
+// slabs of a tile that do hold one are checked again per string: a string-start
+// bitmap in LDS, the lookups at position i using prev1/prev2/prev3 only when they
+// belong to the string of i, and each string end getting the end check on its own
+// last bytes.  Lanes that see an error record, per position, a bit in one of two LDS
+// bitmaps (regular error / end-check error).  Then the wave writes the result of
+// every string whose end lies in the tile: its first detection is the first bit in
+// its own range.  A string that runs across tiles carries its first detection in a
+// wave-uniform register; one that runs across waves gets a partial minimum from every
+// wave it touches, in a workspace slot of the wave holding its start, and the last of
+// those waves to arrive (an arrival count kept in the same 64-bit word) writes its
+// result and resets the slot, so the workspace is clean again when the kernel ends.
 #include "common.hpp"
 #include "lookup.hpp"
 
@@ -39,41 +40,101 @@ constexpr int kTile = kU * 1024;            // bytes per tile (one wave)
 constexpr int kMaskPad = 16;                // mask bytes kept before the tile (last 4 used)
 constexpr int kOffCap = 128;                // window boundaries cached in LDS for the error path
 
+// Pointers to global memory, typed so: every access compiles to a global (not flat)
+// instruction, whose completion an LDS access never has to wait for.
+template <class T>
+using gptr = T __attribute__((address_space(1)))*;
+
+struct DevArgs {
+  gptr<const uint8_t> data;
+  gptr<const int64_t> offsets;
+  int64_t n;
+  gptr<unsigned long long> slot;
+  gptr<uint8_t> flags;
+  gptr<int64_t> first_err;
+};
+
 // Arguments come by value, or from a device parameter block when pa is not null
 // (graph replays: the captured launches keep pa, only the block's contents change).
-__device__ __forceinline__ BatchArgs args_of(const BatchArgs& a, const BatchArgs* pa) { return pa ? *pa : a; }
+// The buffers are device or pinned host memory, never LDS or scratch.
+__device__ __forceinline__ DevArgs args_of(const BatchArgs& a0, const BatchArgs* pa) {
+  const BatchArgs a = pa ? *pa : a0;
+  return DevArgs{(gptr<const uint8_t>)a.data, (gptr<const int64_t>)a.offsets, a.n,
+                 (gptr<unsigned long long>)a.slot, (gptr<uint8_t>)a.flags, (gptr<int64_t>)a.first_err};
+}
 
-// First k in [0, n] with offsets[k] >= target (offsets[n] >= target is guaranteed by the caller).
-__device__ int64_t wave_lower_bound(const int64_t* __restrict__ offsets, int64_t n, int64_t target, int lane) {
-  int64_t lo = 0, hi = n;  // answer in [lo, hi]
-  while (lo < hi) {
+// Wave-uniform 64-bit value kept in scalar registers.
+__device__ __forceinline__ int64_t uniform(int64_t v) {
+  const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi32 = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi32 << 32) | lo32);
+}
+
+// 64-bit value of lane `src` (0..63) of the wave.
+__device__ __forceinline__ int64_t lane_value(int64_t x, int src) {
+  const int addr = src << 2;
+  const uint32_t l = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)x);
+  const uint32_t h = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)h << 32) | l);
+}
+
+// k0 = the first k in [0, n] with offsets[k] >= target (offsets[n] >= target is
+// guaranteed by the caller), and v = offsets[k0 + lane] (INT64_MAX past n): the
+// window of boundaries that the wave's first tile scans.  Each round is one
+// dependent load per lane, so the rounds are kept few: the first probes 64 indices
+// 128 apart around the index that the byte position suggests (string lengths are
+// roughly stationary in a batch); when the answer is outside them, 64-ary rounds
+// narrow the remaining range; the last round reads the remaining at most 128
+// indices together with the 64 after them, so the window needs no extra round.
+__device__ int64_t wave_window(gptr<const int64_t> offsets, int64_t n, int64_t off_lo, int64_t off_hi,
+                               int64_t target, int lane, int64_t& v) {
+  constexpr int64_t kGap = 128;
+  int64_t lo = 0, hi = n;  // the answer lies in [lo, hi]
+  if (n > kGap) {
+    double f = off_hi > off_lo ? (double)(target - off_lo) / (double)(off_hi - off_lo) : 0.0;
+    f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+    int64_t g = (int64_t)(f * (double)n) - 32 * kGap;
+    g = uniform(g < 0 ? 0 : (g > n - 1 ? n - 1 : g));  // first probe, in [0, n)
+    const int64_t idx = g + (int64_t)lane * kGap;
+    const int c = __popcll(__ballot(idx < n && offsets[idx] < target));  // probes below target
+    if (c > 0) lo = g + (int64_t)(c - 1) * kGap + 1;
+    if (c < 64 && g + (int64_t)c * kGap < n) hi = g + (int64_t)c * kGap;  // that probe is >= target
+  }
+  while (hi - lo > kGap) {
     const int64_t step = (hi - lo + 63) / 64;
     const int64_t idx = lo + (int64_t)lane * step;
-    const bool below = idx < hi && offsets[idx] < target;
-    const int c = __popcll(__ballot(below));
+    const int c = __popcll(__ballot(idx < hi && offsets[idx] < target));
     const int64_t new_lo = c == 0 ? lo : lo + (int64_t)(c - 1) * step + 1;
-    int64_t new_hi = lo + (int64_t)c * step;
+    const int64_t new_hi = lo + (int64_t)c * step;
     lo = new_lo;
     hi = new_hi < hi ? new_hi : hi;
   }
-  return lo;
+  const int64_t i0 = lo + lane;
+  const int64_t w0 = i0 <= n ? offsets[i0] : INT64_MAX;
+  const int64_t w1 = i0 + 64 <= n ? offsets[i0 + 64] : INT64_MAX;
+  const int64_t w2 = i0 + 128 <= n ? offsets[i0 + 128] : INT64_MAX;
+  const int c = __popcll(__ballot(i0 < hi && w0 < target)) + __popcll(__ballot(i0 + 64 < hi && w1 < target));
+  // offsets[lo + c + lane] sits in w[(lane + c) / 64] of lane (lane + c) % 64
+  const int q = c >> 6, r = c & 63;
+  const int64_t wa = q == 0 ? w0 : (q == 1 ? w1 : w2), wb = q == 0 ? w1 : w2;
+  const int src = (lane + r) & 63;
+  const int64_t va = lane_value(wa, src), vb = lane_value(wb, src);
+  v = lane + r < 64 ? va : vb;
+  return lo + c;
 }
 
-// Bytes [q, q+4) of the batch range [lo, hi) as a dword, zero outside the range.
-__device__ uint32_t range_dword(const uint8_t* __restrict__ data, int64_t q, int64_t lo, int64_t hi) {
-  uint32_t v = 0;
-  for (int b = 0; b < 4; ++b)
-    if (q + b >= lo && q + b < hi) v |= (uint32_t)data[q + b] << (8 * b);
+// The 16-byte chunk at c (16-byte aligned address), loaded only when one of its bytes
+// is in the batch range [lo, hi), so that it lies in a page holding batch bytes.
+__device__ __forceinline__ u32x4 edge_load(gptr<const uint8_t> data, int64_t c, int64_t lo, int64_t hi) {
+  u32x4 v = u32x4{0, 0, 0, 0};
+  if (c + 16 > lo && c < hi) v = *reinterpret_cast<gptr<const u32x4>>(data + c);
   return v;
 }
 
-// 16-byte chunk at c (16-byte aligned address) with bytes outside [lo, hi) zeroed.  The
-// aligned 16 bytes are loaded only when one of them is in the range, so they lie in
-// a page that holds batch bytes.
-__device__ u32x4 edge_chunk(const uint8_t* __restrict__ data, int64_t c, int64_t lo, int64_t hi) {
-  if (c + 16 <= lo || c >= hi) return u32x4{0, 0, 0, 0};
-  u32x4 v = *reinterpret_cast<const u32x4*>(data + c);
+// Bytes of chunk v (at c) outside [lo, hi) set to zero.
+__device__ __forceinline__ u32x4 edge_mask(u32x4 v, int64_t c, int64_t lo, int64_t hi) {
   uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int64_t q = c + 4 * j;
     int64_t a = lo - q, b = hi - q;  // keep bytes [a, b) of this dword
@@ -86,22 +147,35 @@ __device__ u32x4 edge_chunk(const uint8_t* __restrict__ data, int64_t c, int64_t
 }
 
 // Start offset of string k, for k in [k0, n] (LDS when cached).
-__device__ __forceinline__ int64_t boundary(int64_t k, const int64_t* __restrict__ offsets, int64_t k0, int64_t k1,
+__device__ __forceinline__ int64_t boundary(int64_t k, gptr<const int64_t> offsets, int64_t k0, int64_t k1,
                                             const int64_t* soff) {
   return (k >= k0 && k < k0 + kOffCap && k < k1) ? soff[k - k0] : offsets[k];
 }
 
 // Loads of one tile: interior tiles read whole chunks (non-temporal); tiles at the
-// edges of the batch range read through edge_chunk.
-__device__ __forceinline__ void batch_load(u32x4 (&x)[kU], const uint8_t* __restrict__ data, int64_t ts, int64_t lo,
+// edges of the batch range read the chunks that hold batch bytes, and batch_mask
+// clears the bytes outside the range (right away, or for a wave's first tile after
+// the boundary search, so the loads stay in flight during it).
+__device__ __forceinline__ bool edge_tile(int64_t ts, int64_t lo, int64_t hi) {
+  return !(ts - 4 >= lo && ts + kTile <= hi);
+}
+
+__device__ __forceinline__ void batch_load(u32x4 (&x)[kU], gptr<const uint8_t> data, int64_t ts, int64_t lo,
                                            int64_t hi, int lane) {
-  if (ts - 4 >= lo && ts + kTile <= hi) {
+  if (!edge_tile(ts, lo, hi)) {
 #pragma unroll
     for (int u = 0; u < kU; ++u)
-      x[u] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(data + ts + u * 1024 + lane * 16));
+      x[u] = __builtin_nontemporal_load(reinterpret_cast<gptr<const u32x4>>(data + ts + u * 1024 + lane * 16));
   } else {
 #pragma unroll
-    for (int u = 0; u < kU; ++u) x[u] = edge_chunk(data, ts + u * 1024 + lane * 16, lo, hi);
+    for (int u = 0; u < kU; ++u) x[u] = edge_load(data, ts + u * 1024 + lane * 16, lo, hi);
+  }
+}
+
+__device__ __forceinline__ void batch_mask(u32x4 (&x)[kU], int64_t ts, int64_t lo, int64_t hi, int lane) {
+  if (edge_tile(ts, lo, hi)) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) x[u] = edge_mask(x[u], ts + u * 1024 + lane * 16, lo, hi);
   }
 }
 
@@ -154,8 +228,10 @@ __device__ __forceinline__ uint32_t nonzero_bytes(uint32_t e) {
 
 // First detection d (relative) -> first-error offset s (section 6.3 applied backwards:
 // the latest k in [d-3, d] that does not cut a character), for a string of length
-// len whose bytes are b[0..len).  The six bytes before d are read at once.
-__device__ __forceinline__ int64_t resolve_first_error(const uint8_t* b, int64_t len, int64_t d) {
+// len whose bytes are b[0..len) (in global memory or LDS).  The six bytes before d are
+// read at once.
+template <class P>
+__device__ __forceinline__ int64_t resolve_first_error(P b, int64_t len, int64_t d) {
   uint32_t w[7];  // w[i] = byte d-i (0 outside the string)
 #pragma unroll
   for (int i = 1; i <= 6; ++i) {
@@ -168,7 +244,8 @@ __device__ __forceinline__ int64_t resolve_first_error(const uint8_t* b, int64_t
   return d;
 }
 
-__device__ __forceinline__ void write_result(const BatchArgs& a, int64_t k, const uint8_t* b, int64_t len, int64_t d) {
+template <class P>
+__device__ __forceinline__ void write_result(const DevArgs& a, int64_t k, P b, int64_t len, int64_t d) {
   if (d == kNoneRel) {
     a.flags[k] = 1;
     a.first_err[k] = -1;
@@ -176,13 +253,6 @@ __device__ __forceinline__ void write_result(const BatchArgs& a, int64_t k, cons
     a.flags[k] = 0;
     a.first_err[k] = resolve_first_error(b, len, d);
   }
-}
-
-// Wave-uniform 64-bit value kept in scalar registers.
-__device__ __forceinline__ int64_t uniform(int64_t v) {
-  const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi32 = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
-  return (int64_t)(((uint64_t)hi32 << 32) | lo32);
 }
 
 // Wave holding position p (tiles are dealt out in runs of `per`).
@@ -199,10 +269,10 @@ constexpr uint64_t kSlotNone = (1ull << kSlotShift) - 1;
 // empties the slot.  Lane 0.  A contribution that does not lower the slot's
 // detection (the usual case: none) is a plain atomic add of one arrival, so the
 // many waves inside one long string do not contend in compare-and-swap loops.
-__device__ void cross_wave(const BatchArgs& a, int64_t k, int64_t st, int64_t en, int64_t d, int64_t c0,
+__device__ void cross_wave(const DevArgs& a, int64_t k, int64_t st, int64_t en, int64_t d, int64_t c0,
                            int64_t per) {
   const int64_t ws = wave_of(st, c0, per), we = wave_of(en, c0, per);
-  unsigned long long* slot = a.slot + ws;
+  const gptr<unsigned long long> slot = a.slot + ws;
   const uint64_t mine = d == kNoneRel ? kSlotNone : (uint64_t)d;
   uint64_t old = 0;
   bool done = false;
@@ -210,32 +280,51 @@ __device__ void cross_wave(const BatchArgs& a, int64_t k, int64_t st, int64_t en
     old = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     while ((old & kSlotNone) > mine) {
       const uint64_t nw = (old & ~kSlotNone) + (1ull << kSlotShift) + mine;
-      const uint64_t seen = atomicCAS(slot, (unsigned long long)old, (unsigned long long)nw);
-      if (seen == old) { done = true; break; }
+      unsigned long long seen = old;
+      if (__hip_atomic_compare_exchange_strong(slot, &seen, (unsigned long long)nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)) {
+        done = true;
+        break;
+      }
       old = seen;
     }
   }
-  if (!done) old = atomicAdd(slot, 1ull << kSlotShift);
+  if (!done) old = __hip_atomic_fetch_add(slot, 1ull << kSlotShift, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if ((int64_t)(old >> kSlotShift) + 1 == we - ws + 1) {
     const uint64_t prev = old & kSlotNone;
     const uint64_t best = prev < mine ? prev : mine;
-    atomicExch(slot, (unsigned long long)kSlotNone);
+    __hip_atomic_exchange(slot, (unsigned long long)kSlotNone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     write_result(a, k, a.data + st, en - st, best == kSlotNone ? kNoneRel : (int64_t)best);
   }
 }
 
+// Byte masks (0xFF per set bit) of four start bits.
+__device__ __forceinline__ uint32_t bits_to_bytes(uint32_t nib) { return ((nib * 0x00204081u) & 0x01010101u) * 0xFFu; }
+
 // One wave per workgroup; each wave validates a contiguous run of tiles.  The data
 // and the first boundary offsets of tile t+1 are requested right after tile t's
 // boundary scan, before tile t is classified, so their latency overlaps it.
+//
+// A tile is first checked as plain text (the single-buffer checks, bytes of other
+// strings included), and at every string boundary b in [ts-2, te) the end check of
+// section 6.3 is applied to the plain bytes before b.  Where that check passes, the
+// bytes before b cannot change any check at b, b+1 or b+2 (the previous character is
+// complete), so the plain checks equal the per-string ones there; elsewhere they are
+// the same computation.  A tile with no plain error and no failed boundary check thus
+// holds only valid strings.  In the other tiles, the 1 KiB slabs holding a plain error
+// or a position b..b+2 of a failed check are checked again per string (a string-start
+// bitmap in LDS, the bytes of other strings masked to zero); the remaining slabs have
+// no error under either form.
 __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* pa) {
-  const BatchArgs a = args_of(a0, pa);
-  __shared__ __align__(16) uint8_t smask[kTile + kMaskPad];  // string starts at positions [ts-16, te)
-  __shared__ int64_t soff[kOffCap];                           // offsets[k0 ..] of the window
-  __shared__ uint32_t regm[kMaskWords];                       // regular error at tile position r
-  __shared__ uint32_t endm[kMaskWords];                       // end-check error at tile position r
+  const DevArgs a = args_of(a0, pa);
+  __shared__ __align__(16) uint8_t sbytes[kTile + kMaskPad];  // tile positions [-16, kTile)
+  __shared__ uint32_t sbits[kMaskWords + 1];                   // string starts at positions [-32, kTile)
+  __shared__ int64_t soff[kOffCap];                            // offsets[k0 ..] of the window
+  __shared__ uint32_t regm[kMaskWords];                        // regular error at tile position r
+  __shared__ uint32_t endm[kMaskWords];                        // end-check error at tile position r
   const int lane = threadIdx.x;
-  const int64_t* __restrict__ offsets = a.offsets;
-  const uint8_t* __restrict__ data = a.data;
+  const gptr<const int64_t> offsets = a.offsets;
+  const gptr<const uint8_t> data = a.data;
   // the byte range is read on the device, so one launch shape serves any batch
   const int64_t n = a.n;
   const int64_t lo = uniform(offsets[0]), hi = uniform(offsets[n]);
@@ -249,35 +338,32 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
   const int64_t wave_lo = c0 + t * kTile;
   regm[lane] = regm[lane + 64] = 0u;
   endm[lane] = endm[lane + 64] = 0u;
-  int64_t k0 = uniform(wave_lower_bound(offsets, n, wave_lo - 4, lane));
-  uint32_t carry = range_dword(data, wave_lo - 4, lo, hi);  // the dword before the first tile
+  // the first tile's bytes do not depend on the boundary search: requested before it
+  u32x4 x[kU];
+  batch_load(x, data, wave_lo, lo, hi, lane);
+  const u32x4 before = edge_load(data, wave_lo - 16, lo, hi);  // the 16 bytes before the first tile
+  int64_t v;
+  int64_t k0 = uniform(wave_window(offsets, n, lo, hi, wave_lo - 4, lane, v));
+  batch_mask(x, wave_lo, lo, hi, lane);
+  const u32x4 bm = edge_mask(before, wave_lo - 16, lo, hi);
+  uint32_t carry = bm.w;    // the dword before the first tile
+  uint32_t carry2 = bm.z;   // and the one before that
   const bool lane0 = lane == 0;
   int ascii_skip = 0;
   // the string open at the wave start (it began in an earlier wave) is found in the first window
   int64_t open_k = -2, open_st = 0, open_d = kNoneRel;
 
-  u32x4 x[kU];
-  batch_load(x, data, wave_lo, lo, hi, lane);
-  int64_t v = k0 + lane <= n ? offsets[k0 + lane] : INT64_MAX;
-
   for (; t < t_end; ++t) {
     const int64_t ts = c0 + t * kTile;
     const int64_t te = ts + kTile;
-    // 1. string-start mask of positions [ts-4, te) in LDS; boundaries [k0, k1) of the window.
-    // A tile inside one string (the window's first boundary lies past it) needs neither.
+    // 1. boundaries of the window [ts-4, te): [k0, k1), those in [ts, te): [kb, k1).  A tile
+    // inside one string (the window's first boundary lies past it) has none.
     const bool plain = uniform(v) >= te;
     int64_t cnt = 0, cnt_next = 0, cnt_before = 0;
     if (!plain) {
-#pragma unroll
-      for (int u = 0; u < kU; ++u) reinterpret_cast<u32x4*>(smask + kMaskPad)[u * 64 + lane] = u32x4{0, 0, 0, 0};
-      if (lane0) *reinterpret_cast<u32x4*>(smask) = u32x4{0, 0, 0, 0};
-      __syncthreads();
       for (;;) {
         const bool in = v < te;
-        if (in) {
-          smask[v - ts + kMaskPad] = 0xFF;
-          if (cnt + lane < kOffCap) soff[cnt + lane] = v;
-        }
+        if (in && cnt + lane < kOffCap) soff[cnt + lane] = v;
         const int c = __popcll(__ballot(in));
         cnt_next += __popcll(__ballot(v < te - 4));
         cnt_before += __popcll(__ballot(v < ts));
@@ -287,13 +373,14 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
         v = idx <= n ? offsets[idx] : INT64_MAX;
       }
     }
-    const int64_t k1 = uniform(k0 + cnt);          // boundaries in [ts-4, te): [k0, k1)
-    const int64_t kb = uniform(k0 + cnt_before);   // boundaries in [ts, te): [kb, k1)
+    const int64_t k1 = uniform(k0 + cnt);
+    const int64_t kb = uniform(k0 + cnt_before);
     // 2. request tile t+1 (its window starts at boundary k0 + cnt_next)
     u32x4 nx[kU];
     const int64_t k0n = k0 + cnt_next;
     if (t + 1 < t_end) {
       batch_load(nx, data, te, lo, hi, lane);
+      batch_mask(nx, te, lo, hi, lane);
       if (!plain) v = k0n + lane <= n ? offsets[k0n + lane] : INT64_MAX;  // (plain: the same window)
     }
     __syncthreads();
@@ -303,13 +390,15 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     }
     // 3. the dword before each chunk: lane l-1's last dword (lane 0: lane 63 of the previous slab)
     uint32_t prev[kU];
+    const uint32_t before_tile = carry, before2 = carry2;  // bytes [ts-4, ts) and [ts-8, ts-4)
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const uint32_t rot = (uint32_t)__builtin_amdgcn_mov_dpp((int)x[u].w, kDppWaveRor1, 0xF, 0xF, true);
       prev[u] = lane0 ? carry : rot;
       carry = rot;
     }
-    // 4. checks; a tile that is all ASCII with an ASCII halo cannot hold an error (6.4)
+    carry2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)x[kU - 1].z, kDppWaveRor1, 0xF, 0xF, true);
+    // 4. plain checks; a tile that is all ASCII with an ASCII halo cannot hold an error (6.4)
     bool run = true;
     if (ascii_skip == 0) {
       uint32_t o = 0;
@@ -320,41 +409,63 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     } else {
       --ascii_skip;
     }
-    uint32_t bad = 0;  // bit u: slab u saw a regular or end-check error
+    uint32_t slabs = 0;  // bit u: slab u needs the per-string recheck (wave-uniform)
     if (run) {
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        uint32_t acc = 0, tail = 0;
-        if (plain) {
-          acc = chunk_errors(0u, x[u].x, x[u].y, x[u].z, x[u].w, prev[u]);
-          bad |= acc ? (1u << u) : 0u;
-          continue;
-        }
-        const u32x4 s4 = reinterpret_cast<const u32x4*>(smask + kMaskPad)[u * 64 + lane];
-        const uint32_t sp = *reinterpret_cast<const uint32_t*>(smask + kMaskPad + u * 1024 + lane * 16 - 4);
-        if (__any((s4.x | s4.y | s4.z | s4.w | sp) != 0u)) {
-          MaskedCarry c = masked_halo(prev[u], sp);
-          masked_next(x[u].x, prev[u], s4.x, sp, c, acc, tail);
-          masked_next(x[u].y, x[u].x, s4.y, s4.x, c, acc, tail);
-          masked_next(x[u].z, x[u].y, s4.z, s4.y, c, acc, tail);
-          masked_next(x[u].w, x[u].z, s4.w, s4.z, c, acc, tail);
-        } else {  // no string starts in the slab or the 4 bytes before it: the plain checks
-          acc = chunk_errors(0u, x[u].x, x[u].y, x[u].z, x[u].w, prev[u]);
-        }
-        bad |= (acc | tail) ? (1u << u) : 0u;
+      for (int u = 0; u < kU; ++u)
+        if (__any(chunk_errors(0u, x[u].x, x[u].y, x[u].z, x[u].w, prev[u]) != 0u)) slabs |= 1u << u;
+    }
+    // 5. the tile's bytes (and the 8 before it) in LDS, for the boundary checks, the per-string
+    // recheck and the resolution
+    if (!plain || slabs != 0u) {
+#pragma unroll
+      for (int u = 0; u < kU; ++u) reinterpret_cast<u32x4*>(sbytes + kMaskPad)[u * 64 + lane] = x[u];
+      if (lane0) *reinterpret_cast<uint2*>(sbytes + kMaskPad - 8) = make_uint2(before2, before_tile);
+      __syncthreads();
+    }
+    const uint8_t* tile_bytes = sbytes + kMaskPad;  // tile_bytes[p - ts] = byte p, for p >= ts - 8
+    // 6. the end check (6.3) on the plain bytes before every string boundary in [ts-2, te)
+    // A failed check at b leaves the plain checks at b, b+1 and b+2 unreliable: their slabs are rechecked.
+    uint32_t end_slabs = 0;
+    for (int64_t k = k0 + lane; k - lane < k1; k += 64) {
+      if (k < k1) {
+        const int r = (int)(boundary(k, offsets, k0, k1, soff) - ts);  // >= -4
+        if (r >= -2 && (tile_bytes[r - 1] >= 0xC0 || tile_bytes[r - 2] >= 0xE0 || tile_bytes[r - 3] >= 0xF0))
+          end_slabs |= (1u << ((r < 0 ? 0 : r) >> 10)) | (1u << ((r + 2 < kTile ? r + 2 : kTile - 1) >> 10));
       }
     }
-    const bool tile_bad = __any(bad != 0);
-    // 5. rare: per-position error bits of the slabs that saw an error
-    if (__builtin_expect(bad != 0, 0)) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (__any((end_slabs >> u) & 1u)) slabs |= 1u << u;
+    const bool tile_bad = slabs != 0u;
+    // 7. rare: per-string checks (other strings' bytes masked) giving per-position error bits
+    WordSummary nz{0, 0};
+    uint32_t bad = 0;  // bit u: this lane wrote error bits for slab u
+    if (tile_bad) {
+      sbits[lane] = 0u;
+      sbits[lane + 64] = 0u;
+      if (lane0) sbits[kMaskWords] = 0u;
+      __syncthreads();
+      for (int64_t k = k0 + lane; k - lane < k1; k += 64) {
+        if (k < k1) {
+          const int64_t r = boundary(k, offsets, k0, k1, soff) - ts + 32;  // bit index, >= 28
+          atomicOr(&sbits[r >> 5], 1u << (r & 31));
+        }
+      }
+      __syncthreads();
+#pragma unroll 1
       for (int u = 0; u < kU; ++u) {
-        if (!((bad >> u) & 1)) continue;
-        const u32x4 s4 = plain ? u32x4{0, 0, 0, 0} : reinterpret_cast<const u32x4*>(smask + kMaskPad)[u * 64 + lane];
-        const uint32_t sp =
-            plain ? 0u : *reinterpret_cast<const uint32_t*>(smask + kMaskPad + u * 1024 + lane * 16 - 4);
-        const uint32_t xs[5] = {prev[u], x[u].x, x[u].y, x[u].z, x[u].w};
-        const uint32_t ss[5] = {sp, s4.x, s4.y, s4.z, s4.w};
-        MaskedCarry c = masked_halo(prev[u], sp);
+        if (((slabs >> u) & 1u) == 0u) continue;  // no plain error and no failed boundary check in it
+        const int b = u * 1024 + lane * 16 + 32;  // bit of the lane's first position
+        const uint32_t s16 = (sbits[b >> 5] >> (b & 31)) & 0xFFFFu;
+        const uint32_t sp4 = (b & 31) ? (sbits[b >> 5] >> 12) & 0xFu : sbits[(b >> 5) - 1] >> 28;
+        const uint32_t sp = bits_to_bytes(sp4);
+        const u32x4 xv = reinterpret_cast<const u32x4*>(tile_bytes)[u * 64 + lane];
+        const uint32_t pv = *reinterpret_cast<const uint32_t*>(tile_bytes + u * 1024 + lane * 16 - 4);
+        const uint32_t xs[5] = {pv, xv.x, xv.y, xv.z, xv.w};
+        const uint32_t ss[5] = {sp, bits_to_bytes(s16 & 0xF), bits_to_bytes((s16 >> 4) & 0xF),
+                                bits_to_bytes((s16 >> 8) & 0xF), bits_to_bytes(s16 >> 12)};
+        MaskedCarry c = masked_halo(pv, sp);
         uint32_t rbits = 0, ebits = 0;
         for (int j = 0; j < 4; ++j) {
           uint32_t e = 0, tl = 0;
@@ -362,29 +473,24 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
           rbits |= nonzero_bytes(e) << (4 * j);
           ebits |= nonzero_bytes(tl) << (4 * j);
         }
-        const int64_t base = ts + u * 1024 + lane * 16;
-        if (base - 1 < lo || base + 16 > hi) {  // chunk at an edge of the batch range
-          for (int b = 0; b < 16; ++b) {
-            const int64_t pos = base + b;
-            if (!(pos >= lo && pos < hi)) rbits &= ~(1u << b);
-            if (!(pos - 1 >= lo && pos <= hi)) ebits &= ~(1u << b);
+        if ((rbits | ebits) != 0u) {
+          const int64_t base = ts + u * 1024 + lane * 16;
+          if (base - 1 < lo || base + 16 > hi) {  // chunk at an edge of the batch range
+            for (int q = 0; q < 16; ++q) {
+              const int64_t pos = base + q;
+              if (!(pos >= lo && pos < hi)) rbits &= ~(1u << q);
+              if (!(pos - 1 >= lo && pos <= hi)) ebits &= ~(1u << q);
+            }
           }
+          reinterpret_cast<uint16_t*>(regm)[u * 64 + lane] = (uint16_t)rbits;
+          reinterpret_cast<uint16_t*>(endm)[u * 64 + lane] = (uint16_t)ebits;
+          bad |= 1u << u;
         }
-        reinterpret_cast<uint16_t*>(regm)[u * 64 + lane] = (uint16_t)rbits;
-        reinterpret_cast<uint16_t*>(endm)[u * 64 + lane] = (uint16_t)ebits;
       }
-    }
-    __syncthreads();
-    // the tile's bytes, for resolving first errors of the strings inside it (the mask is spent)
-    const uint8_t* tile_bytes = smask + kMaskPad;
-    if (tile_bad) {
-#pragma unroll
-      for (int u = 0; u < kU; ++u) reinterpret_cast<u32x4*>(smask + kMaskPad)[u * 64 + lane] = x[u];
       __syncthreads();
+      nz = summarize(regm, lane);
     }
-    // 6. results of the strings that end in this tile (end positions in [ts, te))
-    WordSummary nz{0, 0};
-    if (tile_bad) nz = summarize(regm, lane);
+    // 8. results of the strings that end in this tile (end positions in [ts, te))
     if (open_k >= 0) {  // the string open at ts
       const bool ends = kb < k1;
       const int64_t en = ends ? uniform(boundary(kb, offsets, k0, k1, soff)) : te;
@@ -413,7 +519,7 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
       if (k < k1 - 1) {
         const int64_t st = boundary(k, offsets, k0, k1, soff), en = boundary(k + 1, offsets, k0, k1, soff);
         int64_t d = kNoneRel;
-        if (tile_bad && en > st) {
+        if (en > st) {
           const int r = first_bit(regm, nz, (int)(st - ts), (int)(en - ts));
           if (r >= 0) d = ts + r - st;
           if (bit_at(endm, (int)(en - ts)) && en - st < d) d = en - st;
@@ -430,9 +536,10 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
         if (r >= 0) open_d = ts + r - open_st;
       }
     }
-    // 7. clear the bits this lane set, once every lane has read them
-    if (tile_bad) __syncthreads();
-    if (__builtin_expect(bad != 0, 0)) {
+    // 9. clear the error bits this lane set, once every lane has read them
+    if (tile_bad) {
+      __syncthreads();
+#pragma unroll
       for (int u = 0; u < kU; ++u) {
         if ((bad >> u) & 1) {
           reinterpret_cast<uint16_t*>(regm)[u * 64 + lane] = 0;
