@@ -63,6 +63,14 @@ __device__ __forceinline__ DevArgs args_of(const BatchArgs& a0, const BatchArgs*
                  (gptr<unsigned long long>)a.slot, (gptr<uint8_t>)a.flags, (gptr<int64_t>)a.first_err};
 }
 
+// Strings [k0, k1) are valid.
+__device__ __forceinline__ void write_valid(const DevArgs& a, int64_t k0, int64_t k1, int lane) {
+  for (int64_t k = k0 + lane; k < k1; k += 64) {
+    a.flags[k] = 1;
+    a.first_err[k] = -1;
+  }
+}
+
 // Wave-uniform 64-bit value kept in scalar registers.
 __device__ __forceinline__ int64_t uniform(int64_t v) {
   const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -298,6 +306,24 @@ __device__ void cross_wave(const DevArgs& a, int64_t k, int64_t st, int64_t en, 
   }
 }
 
+// The tile's bytes, and the 8 before it, into LDS (sb[kMaskPad + r] = tile byte r).
+__device__ __forceinline__ void stage_tile(uint8_t* sb, const u32x4 (&x)[kU], uint32_t before2, uint32_t before1,
+                                           int lane) {
+#pragma unroll
+  for (int u = 0; u < kU; ++u) reinterpret_cast<u32x4*>(sb + kMaskPad)[u * 64 + lane] = x[u];
+  if (lane == 0) *reinterpret_cast<uint2*>(sb + kMaskPad - 8) = make_uint2(before2, before1);
+  __syncthreads();
+}
+
+// The end check of section 6.3 on the (plain) bytes before the string boundary at tile
+// position r >= -4: the slabs whose checks it makes unreliable when it fails (those of
+// positions r, r+1, r+2), else 0.  Boundaries before -2 belong to the previous tile.
+__device__ __forceinline__ uint32_t end_check_slabs(const uint8_t* tile_bytes, int r) {
+  if (r < -2) return 0u;
+  if (tile_bytes[r - 1] < 0xC0 && tile_bytes[r - 2] < 0xE0 && tile_bytes[r - 3] < 0xF0) return 0u;
+  return (1u << ((r < 0 ? 0 : r) >> 10)) | (1u << ((r + 2 < kTile ? r + 2 : kTile - 1) >> 10));
+}
+
 // Byte masks (0xFF per set bit) of four start bits.
 __device__ __forceinline__ uint32_t bits_to_bytes(uint32_t nib) { return ((nib * 0x00204081u) & 0x01010101u) * 0xFFu; }
 
@@ -352,6 +378,8 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
   int ascii_skip = 0;
   // the string open at the wave start (it began in an earlier wave) is found in the first window
   int64_t open_k = -2, open_st = 0, open_d = kNoneRel;
+  // strings found valid in the previous tile, written during the next one (see step 2)
+  int64_t pend_lo = 0, pend_hi = 0;
 
   for (; t < t_end; ++t) {
     const int64_t ts = c0 + t * kTile;
@@ -375,7 +403,12 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     }
     const int64_t k1 = uniform(k0 + cnt);
     const int64_t kb = uniform(k0 + cnt_before);
-    // 2. request tile t+1 (its window starts at boundary k0 + cnt_next)
+    // a window of at most 63 boundaries is held whole by the lanes: lane l has boundary k0 + l
+    const int64_t vwin = v;
+    // 2. the previous tile's valid strings are written here, before tile t+1 is requested: a
+    // load's wait also waits for every store issued before it, so these stores get a tile's
+    // time to complete.  Then request tile t+1 (its window starts at boundary k0 + cnt_next).
+    write_valid(a, pend_lo, pend_hi, lane);
     u32x4 nx[kU];
     const int64_t k0n = k0 + cnt_next;
     if (t + 1 < t_end) {
@@ -409,35 +442,35 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     } else {
       --ascii_skip;
     }
-    uint32_t slabs = 0;  // bit u: slab u needs the per-string recheck (wave-uniform)
+    uint32_t m = 0;  // bit u: this lane saw slab u fail (a plain error, or a failed end check below)
     if (run) {
 #pragma unroll
       for (int u = 0; u < kU; ++u)
-        if (__any(chunk_errors(0u, x[u].x, x[u].y, x[u].z, x[u].w, prev[u]) != 0u)) slabs |= 1u << u;
+        m |= (chunk_errors(0u, x[u].x, x[u].y, x[u].z, x[u].w, prev[u]) != 0u ? 1u : 0u) << u;
     }
     // 5. the tile's bytes (and the 8 before it) in LDS, for the boundary checks, the per-string
     // recheck and the resolution
-    if (!plain || slabs != 0u) {
-#pragma unroll
-      for (int u = 0; u < kU; ++u) reinterpret_cast<u32x4*>(sbytes + kMaskPad)[u * 64 + lane] = x[u];
-      if (lane0) *reinterpret_cast<uint2*>(sbytes + kMaskPad - 8) = make_uint2(before2, before_tile);
-      __syncthreads();
-    }
     const uint8_t* tile_bytes = sbytes + kMaskPad;  // tile_bytes[p - ts] = byte p, for p >= ts - 8
-    // 6. the end check (6.3) on the plain bytes before every string boundary in [ts-2, te)
-    // A failed check at b leaves the plain checks at b, b+1 and b+2 unreliable: their slabs are rechecked.
-    uint32_t end_slabs = 0;
-    for (int64_t k = k0 + lane; k - lane < k1; k += 64) {
-      if (k < k1) {
-        const int r = (int)(boundary(k, offsets, k0, k1, soff) - ts);  // >= -4
-        if (r >= -2 && (tile_bytes[r - 1] >= 0xC0 || tile_bytes[r - 2] >= 0xE0 || tile_bytes[r - 3] >= 0xF0))
-          end_slabs |= (1u << ((r < 0 ? 0 : r) >> 10)) | (1u << ((r + 2 < kTile ? r + 2 : kTile - 1) >> 10));
+    if (!plain) {
+      stage_tile(sbytes, x, before2, before_tile, lane);
+      // 6. the end check (6.3) on the plain bytes before every string boundary in [ts-2, te).
+      // A failed check at b leaves the plain checks at b, b+1 and b+2 unreliable: their slabs
+      // are rechecked.
+      if (cnt < 64) {
+        if (lane < cnt) m |= end_check_slabs(tile_bytes, (int)(vwin - ts));
+      } else {
+        for (int64_t k = k0 + lane; k - lane < k1; k += 64)
+          if (k < k1) m |= end_check_slabs(tile_bytes, (int)(boundary(k, offsets, k0, k1, soff) - ts));
       }
     }
+    const bool tile_bad = __any(m != 0u);
+    uint32_t slabs = 0;  // bit u: slab u needs the per-string recheck (wave-uniform)
+    if (tile_bad) {
 #pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (__any((end_slabs >> u) & 1u)) slabs |= 1u << u;
-    const bool tile_bad = slabs != 0u;
+      for (int u = 0; u < kU; ++u)
+        if (__any((m >> u) & 1u)) slabs |= 1u << u;
+      if (plain) stage_tile(sbytes, x, before2, before_tile, lane);
+    }
     // 7. rare: per-string checks (other strings' bytes masked) giving per-position error bits
     WordSummary nz{0, 0};
     uint32_t bad = 0;  // bit u: this lane wrote error bits for slab u
@@ -459,14 +492,17 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
         const int b = u * 1024 + lane * 16 + 32;  // bit of the lane's first position
         const uint32_t s16 = (sbits[b >> 5] >> (b & 31)) & 0xFFFFu;
         const uint32_t sp4 = (b & 31) ? (sbits[b >> 5] >> 12) & 0xFu : sbits[(b >> 5) - 1] >> 28;
-        const uint32_t sp = bits_to_bytes(sp4);
+        // the lane's 16 bytes and the dword before them
         const u32x4 xv = reinterpret_cast<const u32x4*>(tile_bytes)[u * 64 + lane];
         const uint32_t pv = *reinterpret_cast<const uint32_t*>(tile_bytes + u * 1024 + lane * 16 - 4);
         const uint32_t xs[5] = {pv, xv.x, xv.y, xv.z, xv.w};
-        const uint32_t ss[5] = {sp, bits_to_bytes(s16 & 0xF), bits_to_bytes((s16 >> 4) & 0xF),
-                                bits_to_bytes((s16 >> 8) & 0xF), bits_to_bytes(s16 >> 12)};
-        MaskedCarry c = masked_halo(pv, sp);
+        uint32_t ss[5];
+        ss[0] = bits_to_bytes(sp4);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ss[j + 1] = bits_to_bytes((s16 >> (4 * j)) & 0xFu);
+        MaskedCarry c = masked_halo(pv, ss[0]);
         uint32_t rbits = 0, ebits = 0;
+#pragma unroll
         for (int j = 0; j < 4; ++j) {
           uint32_t e = 0, tl = 0;
           masked_next(xs[j + 1], xs[j], ss[j + 1], ss[j], c, e, tl);
@@ -490,7 +526,9 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
       __syncthreads();
       nz = summarize(regm, lane);
     }
-    // 8. results of the strings that end in this tile (end positions in [ts, te))
+    // 8. results of the strings that end in this tile (end positions in [ts, te)); those found
+    // valid form the range [pend_lo, pend_hi), written during the next tile
+    pend_lo = pend_hi = kb;
     if (open_k >= 0) {  // the string open at ts
       const bool ends = kb < k1;
       const int64_t en = ends ? uniform(boundary(kb, offsets, k0, k1, soff)) : te;
@@ -500,22 +538,20 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
         if (ends && bit_at(endm, (int)(en - ts)) && en - open_st < open_d) open_d = en - open_st;
       }
       if (ends) {
-        if (lane0) {
-          if (open_st >= wave_lo) write_result(a, open_k, data + open_st, en - open_st, open_d);
-          else cross_wave(a, open_k, open_st, en, open_d, c0, per);
+        if (open_st < wave_lo) {
+          if (lane0) cross_wave(a, open_k, open_st, en, open_d, c0, per);
+        } else if (open_d == kNoneRel) {
+          pend_lo = open_k;  // = kb - 1, written with the tile's valid strings
+        } else if (lane0) {
+          write_result(a, open_k, data + open_st, en - open_st, open_d);
         }
         open_k = -1;
       }
     }
-    for (int64_t j0 = kb; j0 < k1 - 1; j0 += 64) {  // strings that start and end in the tile
+    // strings that start and end in the tile: with no error anywhere in the tile all are valid
+    if (!tile_bad) pend_hi = k1 - 1 > kb ? k1 - 1 : kb;
+    for (int64_t j0 = kb; tile_bad && j0 < k1 - 1; j0 += 64) {
       const int64_t k = j0 + lane;
-      if (!tile_bad) {  // no error anywhere in the tile: every such string is valid
-        if (k < k1 - 1) {
-          a.flags[k] = 1;
-          a.first_err[k] = -1;
-        }
-        continue;
-      }
       if (k < k1 - 1) {
         const int64_t st = boundary(k, offsets, k0, k1, soff), en = boundary(k + 1, offsets, k0, k1, soff);
         int64_t d = kNoneRel;
@@ -552,6 +588,7 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     for (int u = 0; u < kU; ++u) x[u] = nx[u];
     __syncthreads();
   }
+  write_valid(a, pend_lo, pend_hi, lane);
   // the string still open runs into the next wave
   if (open_k >= 0 && lane0) cross_wave(a, open_k, open_st, offsets[open_k + 1], open_d, c0, per);
 }
