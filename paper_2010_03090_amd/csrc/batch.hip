@@ -71,6 +71,15 @@ __device__ __forceinline__ void write_valid(const DevArgs& a, int64_t k0, int64_
   }
 }
 
+// Workgroups are dealt to the XCDs in turn (workgroup b runs on XCD b % kXcds), and
+// each XCD has its own L2.  Numbering the waves so that each XCD's waves hold
+// adjacent runs of tiles keeps the lines that neighbouring waves both read (tile
+// edges, window offsets, boundary search probes) in one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t logical_wave(int64_t b, int64_t g) {
+  return g % kXcds ? b : (b % kXcds) * (g / kXcds) + b / kXcds;
+}
+
 // Wave-uniform 64-bit value kept in scalar registers.
 __device__ __forceinline__ int64_t uniform(int64_t v) {
   const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -91,9 +100,11 @@ __device__ __forceinline__ int64_t lane_value(int64_t x, int src) {
 // window of boundaries that the wave's first tile scans.  Each round is one
 // dependent load per lane, so the rounds are kept few: the first probes 64 indices
 // 128 apart around the index that the byte position suggests (string lengths are
-// roughly stationary in a batch); when the answer is outside them, 64-ary rounds
-// narrow the remaining range; the last round reads the remaining at most 128
-// indices together with the 64 after them, so the window needs no extra round.
+// roughly stationary in a batch), leaving about 3000 indices or more on either side;
+// the probe grid is aligned to 2048 indices, so waves with nearby starts read the
+// same cache lines.  When the answer is outside the probes, 64-ary rounds narrow the
+// remaining range; the last round reads the remaining at most 128 indices together
+// with the 64 after them, so the window needs no extra round.
 __device__ int64_t wave_window(gptr<const int64_t> offsets, int64_t n, int64_t off_lo, int64_t off_hi,
                                int64_t target, int lane, int64_t& v) {
   constexpr int64_t kGap = 128;
@@ -101,8 +112,9 @@ __device__ int64_t wave_window(gptr<const int64_t> offsets, int64_t n, int64_t o
   if (n > kGap) {
     double f = off_hi > off_lo ? (double)(target - off_lo) / (double)(off_hi - off_lo) : 0.0;
     f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
-    int64_t g = (int64_t)(f * (double)n) - 32 * kGap;
-    g = uniform(g < 0 ? 0 : (g > n - 1 ? n - 1 : g));  // first probe, in [0, n)
+    int64_t g = (int64_t)(f * (double)n) - 3072;
+    g = g < 0 ? 0 : g / 2048 * 2048;
+    g = uniform(g > n - 1 ? n - 1 : g);  // first probe, in [0, n)
     const int64_t idx = g + (int64_t)lane * kGap;
     const int c = __popcll(__ballot(idx < n && offsets[idx] < target));  // probes below target
     if (c > 0) lo = g + (int64_t)(c - 1) * kGap + 1;
@@ -358,7 +370,7 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
   // tiles cover [c0, hi]: position hi holds the end check of the last string
   const int64_t tiles = (hi + 1 - c0 + kTile - 1) / kTile;
   const int64_t per = (tiles + gridDim.x - 1) / gridDim.x;
-  int64_t t = (int64_t)blockIdx.x * per;
+  int64_t t = logical_wave(blockIdx.x, gridDim.x) * per;
   const int64_t t_end = t + per < tiles ? t + per : tiles;
   if (t >= t_end) return;
   const int64_t wave_lo = c0 + t * kTile;
