@@ -644,3 +644,36 @@ def test_batch_boundary_alphabet_length_4_and_5(u8):
         torch.cuda.synchronize()
         assert np.array_equal(ferr.cpu().numpy(), e_o), n
         assert np.array_equal(flags.cpu().numpy(), f_o), n
+
+
+@pytest.mark.gpu
+def test_batch_length_mix_far_from_stationary(u8):
+    """Length mixes where string index and byte position are far from proportional, so the
+    interpolated first round of each wave's boundary search misses and the search falls
+    back to 64-ary rounds; every launch shape gives the oracle's results."""
+    rng = np.random.default_rng(71)
+    mixes = {
+        # 400k one-byte strings, then 200 strings of 200 KiB
+        "tiny_then_huge": np.concatenate([np.ones(400_000, np.int64), np.full(200, 200_000, np.int64)]),
+        # the reverse
+        "huge_then_tiny": np.concatenate([np.full(200, 200_000, np.int64), np.ones(400_000, np.int64)]),
+        # alternating blocks of 50k short strings and 40 long ones
+        "blocks": np.concatenate([np.concatenate([rng.integers(0, 8, 50_000), rng.integers(50_000, 150_000, 40)])
+                                  for _ in range(6)]).astype(np.int64),
+    }
+    old = u8.get_config()
+    try:
+        for name, lens in mixes.items():
+            for err in (0.0, 0.02):
+                say(f"case: length mix {name}, err {err}")
+                data, offsets, _ = synth.batch_from_lengths(lens, "mixed", 72, err_frac=err)
+                f_o, e_o = oracle.first_error_batch(data, offsets)
+                d_data, d_off = dev(data), dev(offsets)
+                for waves in (4, 16, 48):
+                    u8.set_config(batch_waves_per_cu=waves)
+                    flags, ferr = u8.validate_batch(d_data, d_off)
+                    torch.cuda.synchronize()
+                    assert np.array_equal(ferr.cpu().numpy(), e_o), (name, err, waves)
+                    assert np.array_equal(flags.cpu().numpy(), f_o), (name, err, waves)
+    finally:
+        u8.set_config(**old)

@@ -131,3 +131,28 @@ def test_lookup_model_with_ascii_blocks_on_longer_inputs():
         if seed % 2:
             synth.inject_random(buf, seed)
         assert lm.validate(bytes(buf)) == (oracle.first_error(buf) < 0), (seed, variant, n)
+
+
+def test_plain_and_per_string_checks_agree_after_a_complete_character():
+    """The reading behind the batch kernel's plain-first pass: at a string boundary b whose
+    preceding bytes pass the section 6.3 end check (the earlier string ends with a complete
+    character), the checks of sections 6.1-6.2 at b, b+1 and b+2 flag an error exactly when
+    they do with the bytes before b replaced by zeros (the start state of section 6).  A
+    check at b+3 or later reads no byte before b.  Exhaustive over three bytes on either
+    side of b from an alphabet with a member of every byte class; where the end check fails
+    the two forms do differ, so the condition is needed."""
+    tri = ALPHA[np.indices((ALPHA.size,) * 3).reshape(3, -1).T]  # every 3-byte sequence
+    open_at_b = lm.is_incomplete(tri)
+
+    def agree(before):
+        rows = np.concatenate([np.repeat(before, tri.shape[0], 0), np.tile(tri, (before.shape[0], 1))], 1)
+        masked_rows = rows.copy()
+        masked_rows[:, :3] = 0
+        plain = lm.position_errors(rows)[:, 3:6] != 0
+        masked = lm.position_errors(masked_rows)[:, 3:6] != 0
+        return (plain == masked).all(axis=1)
+
+    complete = tri[~open_at_b]
+    for i in range(0, complete.shape[0], 512):
+        assert agree(complete[i:i + 512]).all()
+    assert not agree(tri[open_at_b][::97]).all()
