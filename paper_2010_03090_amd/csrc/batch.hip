@@ -16,11 +16,13 @@
 // ends with a complete character, and then the checks at the boundary and the two
 // positions after it give the same verdict whether or not the bytes of the earlier
 // string are masked to zero; so a tile with neither a plain error nor a failed end
-// check holds only valid strings (the common case, written out directly).  The 1 KiB
-// slabs of a tile that do hold one are checked again per string: a string-start
-// bitmap in LDS, the lookups at position i using prev1/prev2/prev3 only when they
-// belong to the string of i, and each string end getting the end check on its own
-// last bytes.  Lanes that see an error record, per position, a bit in one of two LDS
+// check holds only valid strings (the common case, written out directly).  In the 1 KiB
+// slabs of a tile that do hold one, per-position error bits are needed: where no failed
+// end check reaches the slab, the plain checks give them (by the same agreement); the
+// other slabs are checked again per string: a string-start bitmap in LDS, the lookups
+// at position i using prev1/prev2/prev3 only when they belong to the string of i, and
+// each string end getting the end check on its own last bytes.  Lanes that see an
+// error record, per position, a bit in one of two LDS
 // bitmaps (regular error / end-check error).  Then the wave writes the result of
 // every string whose end lies in the tile: its first detection is the first bit in
 // its own range.  A string that runs across tiles carries its first detection in a
@@ -454,7 +456,8 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     } else {
       --ascii_skip;
     }
-    uint32_t m = 0;  // bit u: this lane saw slab u fail (a plain error, or a failed end check below)
+    // bit u: this lane saw a plain error in slab u; bit 4 + u: a failed end check below reaches slab u
+    uint32_t m = 0;
     if (run) {
 #pragma unroll
       for (int u = 0; u < kU; ++u)
@@ -469,57 +472,73 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
       // A failed check at b leaves the plain checks at b, b+1 and b+2 unreliable: their slabs
       // are rechecked.
       if (cnt < 64) {
-        if (lane < cnt) m |= end_check_slabs(tile_bytes, (int)(vwin - ts));
+        if (lane < cnt) m |= end_check_slabs(tile_bytes, (int)(vwin - ts)) << 4;
       } else {
         for (int64_t k = k0 + lane; k - lane < k1; k += 64)
-          if (k < k1) m |= end_check_slabs(tile_bytes, (int)(boundary(k, offsets, k0, k1, soff) - ts));
+          if (k < k1) m |= end_check_slabs(tile_bytes, (int)(boundary(k, offsets, k0, k1, soff) - ts)) << 4;
       }
     }
     const bool tile_bad = __any(m != 0u);
-    uint32_t slabs = 0;  // bit u: slab u needs the per-string recheck (wave-uniform)
+    uint32_t slabs = 0;   // bit u: slab u needs per-position error bits (wave-uniform)
+    uint32_t mslabs = 0;  // bit u: ... from the per-string (masked) checks
     if (tile_bad) {
 #pragma unroll
-      for (int u = 0; u < kU; ++u)
+      for (int u = 0; u < kU; ++u) {
         if (__any((m >> u) & 1u)) slabs |= 1u << u;
+        if (__any((m >> (4 + u)) & 1u)) mslabs |= 1u << u;
+      }
+      slabs |= mslabs;
       if (plain) stage_tile(sbytes, x, before2, before_tile, lane);
     }
-    // 7. rare: per-string checks (other strings' bytes masked) giving per-position error bits
+    // 7. rare: per-position error bits of the failing slabs.  Where no failed end check
+    // reaches a slab, its plain checks are the per-string ones (see above); the others are
+    // checked with the bytes of other strings masked to zero, from a string-start bitmap.
     WordSummary nz{0, 0};
     uint32_t bad = 0;  // bit u: this lane wrote error bits for slab u
     if (tile_bad) {
-      sbits[lane] = 0u;
-      sbits[lane + 64] = 0u;
-      if (lane0) sbits[kMaskWords] = 0u;
-      __syncthreads();
-      for (int64_t k = k0 + lane; k - lane < k1; k += 64) {
-        if (k < k1) {
-          const int64_t r = boundary(k, offsets, k0, k1, soff) - ts + 32;  // bit index, >= 28
-          atomicOr(&sbits[r >> 5], 1u << (r & 31));
+      if (mslabs) {
+        sbits[lane] = 0u;
+        sbits[lane + 64] = 0u;
+        if (lane0) sbits[kMaskWords] = 0u;
+        __syncthreads();
+        for (int64_t k = k0 + lane; k - lane < k1; k += 64) {
+          if (k < k1) {
+            const int64_t r = boundary(k, offsets, k0, k1, soff) - ts + 32;  // bit index, >= 28
+            atomicOr(&sbits[r >> 5], 1u << (r & 31));
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
 #pragma unroll 1
       for (int u = 0; u < kU; ++u) {
-        if (((slabs >> u) & 1u) == 0u) continue;  // no plain error and no failed boundary check in it
-        const int b = u * 1024 + lane * 16 + 32;  // bit of the lane's first position
-        const uint32_t s16 = (sbits[b >> 5] >> (b & 31)) & 0xFFFFu;
-        const uint32_t sp4 = (b & 31) ? (sbits[b >> 5] >> 12) & 0xFu : sbits[(b >> 5) - 1] >> 28;
+        if (((slabs >> u) & 1u) == 0u) continue;  // no plain error and no failed end check in it
         // the lane's 16 bytes and the dword before them
         const u32x4 xv = reinterpret_cast<const u32x4*>(tile_bytes)[u * 64 + lane];
         const uint32_t pv = *reinterpret_cast<const uint32_t*>(tile_bytes + u * 1024 + lane * 16 - 4);
-        const uint32_t xs[5] = {pv, xv.x, xv.y, xv.z, xv.w};
-        uint32_t ss[5];
-        ss[0] = bits_to_bytes(sp4);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) ss[j + 1] = bits_to_bytes((s16 >> (4 * j)) & 0xFu);
-        MaskedCarry c = masked_halo(pv, ss[0]);
         uint32_t rbits = 0, ebits = 0;
+        if ((mslabs >> u) & 1u) {
+          const int b = u * 1024 + lane * 16 + 32;  // bit of the lane's first position
+          const uint32_t s16 = (sbits[b >> 5] >> (b & 31)) & 0xFFFFu;
+          const uint32_t sp4 = (b & 31) ? (sbits[b >> 5] >> 12) & 0xFu : sbits[(b >> 5) - 1] >> 28;
+          const uint32_t xs[5] = {pv, xv.x, xv.y, xv.z, xv.w};
+          uint32_t ss[5];
+          ss[0] = bits_to_bytes(sp4);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          uint32_t e = 0, tl = 0;
-          masked_next(xs[j + 1], xs[j], ss[j + 1], ss[j], c, e, tl);
-          rbits |= nonzero_bytes(e) << (4 * j);
-          ebits |= nonzero_bytes(tl) << (4 * j);
+          for (int j = 0; j < 4; ++j) ss[j + 1] = bits_to_bytes((s16 >> (4 * j)) & 0xFu);
+          MaskedCarry c = masked_halo(pv, ss[0]);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            uint32_t e = 0, tl = 0;
+            masked_next(xs[j + 1], xs[j], ss[j + 1], ss[j], c, e, tl);
+            rbits |= nonzero_bytes(e) << (4 * j);
+            ebits |= nonzero_bytes(tl) << (4 * j);
+          }
+        } else {
+          Carry c;
+          rbits = nonzero_bytes(errors_first(0u, xv.x, pv, c));
+          rbits |= nonzero_bytes(errors_next(0u, xv.y, xv.x, c)) << 4;
+          rbits |= nonzero_bytes(errors_next(0u, xv.z, xv.y, c)) << 8;
+          rbits |= nonzero_bytes(errors_next(0u, xv.w, xv.z, c)) << 12;
         }
         if ((rbits | ebits) != 0u) {
           const int64_t base = ts + u * 1024 + lane * 16;
