@@ -178,12 +178,12 @@ int utf8v_validate_ex(const uint8_t* buf, size_t len, int64_t* first_err, void* 
   Workspace* ws = nullptr;
   int rc = workspace(st, &ws);
   if (rc) return rc;
-  // the result slot and its host copy are the workspace's: one synchronous call per stream at a time
+  // the kernel writes the result straight into the workspace's pinned host word (no copy
+  // step after it); one synchronous call per stream at a time
   std::lock_guard<std::mutex> lk(ws->mu);
-  rc = enqueue_single(buf, len, nullptr, st, &ws);
+  rc = enqueue_single(buf, len, ws->host, st, &ws);
   if (rc) return rc;
-  hipError_t e = hipMemcpyAsync(ws->host, ws->result, sizeof(int64_t), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipError_t e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e);
   const int64_t r = *ws->host;
   if (first_err) *first_err = r;
