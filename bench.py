@@ -338,7 +338,13 @@ def bench_batch(u8, lib, synth, torch, dev, stream, sh, args):
     log(f"batch inputs ready in {time.time() - t0:.1f}s: {data.size} bytes")
     fn = lib.utf8v_validate_batch_async
     nstr = args.batch_strings
-    tuned = None if args.no_autotune else autotune_batch(u8, lib, td, to, nstr, flags, ferr)
+    tuned = None
+    if not args.no_autotune:  # tuned on a batch of the same shape from another seed
+        t_data, t_off, _ = synth.lognormal_batch(args.batch_strings, 12)
+        t_td, t_to = torch.from_numpy(t_data).to(dev), torch.from_numpy(t_off).to(dev)
+        tuned = autotune_batch(u8, lib, t_td, t_to, nstr, flags, ferr)
+        tuned["tuning_seed"] = 12
+        del t_data, t_off, t_td, t_to
 
     def run():
         rc = fn(td.data_ptr(), to.data_ptr(), nstr, flags.data_ptr(), ferr.data_ptr(), sh)
@@ -544,10 +550,14 @@ def bench_copy(u8, synth, torch, dev, stream, args):
 def bench_heavy(u8, lib, synth, torch, dev, stream, sh, args):
     """20,000 strings, Pareto lengths (alpha 1.1, clipped at 64 MiB), per-string valid variant, 0.5% errors.
 
-    x_m = 1 KiB gives ~125 MiB in total; x_m = 34 KiB gives ~4 GiB.  Timed through
-    the direct launch and the captured-graph entry point.
+    x_m = 1 KiB gives ~125 MiB in total; x_m = 34 KiB gives ~4 GiB.  Each batch's launch
+    shape is autotuned on a batch of the same shape from another seed (unless
+    --no-autotune); timed through the direct
+    launch and the captured-graph entry point.  The launch configuration is restored
+    afterwards.
     """
     rows = []
+    saved = u8.get_config()
     for name, xm in (("xm_1KiB", 1024.0), ("xm_34KiB", 34 * 1024.0)):
         t0 = time.time()
         data, offsets, expected = synth.pareto_batch(20_000, 3, xm=xm)
@@ -560,6 +570,18 @@ def bench_heavy(u8, lib, synth, torch, dev, stream, sh, args):
         log(f"heavy-tail {name}: {int(offsets[-1]) / 2**20:.0f} MiB ready in {time.time() - t0:.1f}s")
         row = {"workload": name, "payload_bytes": int(offsets[-1] - offsets[0]),
                "largest_string": int(np.diff(offsets).max())}
+        u8.set_config(**saved)
+        if not args.no_autotune:  # tuned on a batch of the same shape from another seed
+            t_data, t_off, _ = synth.pareto_batch(20_000, 13, xm=xm)
+            t_td, t_to = torch.from_numpy(t_data).to(dev), torch.from_numpy(t_off).to(dev)
+            t_n = t_off.size - 1
+            t_flags = torch.empty(t_n, dtype=torch.uint8, device=dev)
+            t_ferr = torch.empty(t_n, dtype=torch.int64, device=dev)
+            row["autotune"] = autotune_batch(u8, lib, t_td, t_to, t_n, t_flags, t_ferr)
+            row["autotune"]["tuning_seed"] = 13
+            del t_data, t_off, t_td, t_to, t_flags, t_ferr
+            torch.cuda.empty_cache()
+        row["launch"] = {"batch_waves_per_cu": u8.get_config()["batch_waves_per_cu"]}
         for mode, fn in (("direct", lib.utf8v_validate_batch_async), ("graph", lib.utf8v_validate_batch_graph)):
             def run():
                 rc = fn(td.data_ptr(), to.data_ptr(), n, flags.data_ptr(), ferr.data_ptr(), sh)
@@ -585,6 +607,7 @@ def bench_heavy(u8, lib, synth, torch, dev, stream, sh, args):
         rows.append(row)
         del td, to, flags, ferr
         torch.cuda.empty_cache()
+    u8.set_config(**saved)
     return rows
 
 
