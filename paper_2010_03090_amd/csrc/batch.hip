@@ -419,6 +419,10 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     const int64_t kb = uniform(k0 + cnt_before);
     // a window of at most 63 boundaries is held whole by the lanes: lane l has boundary k0 + l
     const int64_t vwin = v;
+    // Nothing but the scan's own loads is outstanding here.  Waiting for them now (vmcnt(0);
+    // expcnt and lgkmcnt left alone) keeps the compiler from waiting for v after the stores
+    // below, where, the store count being dynamic, it could only wait for those stores too.
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     // 2. the previous tile's valid strings are written here, before tile t+1 is requested: a
     // load's wait also waits for every store issued before it, so these stores get a tile's
     // time to complete.  Then request tile t+1 (its window starts at boundary k0 + cnt_next).
