@@ -174,6 +174,17 @@ __device__ __forceinline__ int64_t boundary(int64_t k, gptr<const int64_t> offse
   return (k >= k0 && k < k0 + kOffCap && k < k1) ? soff[k - k0] : offsets[k];
 }
 
+// Boundary k of a window whose cnt < 64 boundaries the lanes hold (lane l: boundary
+// k0 + l): a wave-uniform k is read from its lane, a per-lane k by a lane shuffle, so
+// neither waits on memory.  (A read that may come from either LDS or global memory
+// makes the compiler wait for every outstanding global load, the next tile's included.)
+__device__ __forceinline__ int64_t window_uniform(int64_t vwin, int64_t k, int64_t k0) {
+  const int l = (int)(k - k0);
+  const uint32_t lo32 = __builtin_amdgcn_readlane((int)(uint32_t)vwin, l);
+  const uint32_t hi32 = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)vwin >> 32), l);
+  return (int64_t)(((uint64_t)hi32 << 32) | lo32);
+}
+
 // Loads of one tile: interior tiles read whole chunks (non-temporal); tiles at the
 // edges of the batch range read the chunks that hold batch bytes, and batch_mask
 // clears the bytes outside the range (right away, or for a wave's first tile after
@@ -334,7 +345,8 @@ __device__ __forceinline__ void stage_tile(uint8_t* sb, const u32x4 (&x)[kU], ui
 // positions r, r+1, r+2), else 0.  Boundaries before -2 belong to the previous tile.
 __device__ __forceinline__ uint32_t end_check_slabs(const uint8_t* tile_bytes, int r) {
   if (r < -2) return 0u;
-  if (tile_bytes[r - 1] < 0xC0 && tile_bytes[r - 2] < 0xE0 && tile_bytes[r - 3] < 0xF0) return 0u;
+  const uint32_t b1 = tile_bytes[r - 1], b2 = tile_bytes[r - 2], b3 = tile_bytes[r - 3];  // read together
+  if ((b1 < 0xC0) & (b2 < 0xE0) & (b3 < 0xF0)) return 0u;
   return (1u << ((r < 0 ? 0 : r) >> 10)) | (1u << ((r + 2 < kTile ? r + 2 : kTile - 1) >> 10));
 }
 
@@ -505,10 +517,17 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
         sbits[lane + 64] = 0u;
         if (lane0) sbits[kMaskWords] = 0u;
         __syncthreads();
-        for (int64_t k = k0 + lane; k - lane < k1; k += 64) {
-          if (k < k1) {
-            const int64_t r = boundary(k, offsets, k0, k1, soff) - ts + 32;  // bit index, >= 28
+        if (cnt < 64) {
+          if (lane < cnt) {
+            const int r = (int)(vwin - ts) + 32;  // bit index, >= 28
             atomicOr(&sbits[r >> 5], 1u << (r & 31));
+          }
+        } else {
+          for (int64_t k = k0 + lane; k - lane < k1; k += 64) {
+            if (k < k1) {
+              const int64_t r = boundary(k, offsets, k0, k1, soff) - ts + 32;  // bit index, >= 28
+              atomicOr(&sbits[r >> 5], 1u << (r & 31));
+            }
           }
         }
         __syncthreads();
@@ -566,7 +585,9 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     pend_lo = pend_hi = kb;
     if (open_k >= 0) {  // the string open at ts
       const bool ends = kb < k1;
-      const int64_t en = ends ? uniform(boundary(kb, offsets, k0, k1, soff)) : te;
+      const int64_t en = !ends ? te
+                         : cnt < 64 ? window_uniform(vwin, kb, k0)
+                                    : uniform(boundary(kb, offsets, k0, k1, soff));
       if (tile_bad) {
         const int r = first_bit(regm, nz, 0, (int)(en - ts));
         if (r >= 0 && ts + r - open_st < open_d) open_d = ts + r - open_st;
@@ -587,8 +608,16 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     if (!tile_bad) pend_hi = k1 - 1 > kb ? k1 - 1 : kb;
     for (int64_t j0 = kb; tile_bad && j0 < k1 - 1; j0 += 64) {
       const int64_t k = j0 + lane;
+      int64_t st = 0, en = 0;
+      if (cnt < 64) {  // the shuffle reads from every lane: before the branch below
+        st = lane_value(vwin, (int)(k - k0) & 63);
+        en = lane_value(vwin, (int)(k + 1 - k0) & 63);
+      }
       if (k < k1 - 1) {
-        const int64_t st = boundary(k, offsets, k0, k1, soff), en = boundary(k + 1, offsets, k0, k1, soff);
+        if (cnt >= 64) {
+          st = boundary(k, offsets, k0, k1, soff);
+          en = boundary(k + 1, offsets, k0, k1, soff);
+        }
         int64_t d = kNoneRel;
         if (en > st) {
           const int r = first_bit(regm, nz, (int)(st - ts), (int)(en - ts));
@@ -600,7 +629,7 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     }
     if (k1 - 1 >= kb && k1 <= n) {  // the string starting here that runs past te
       open_k = k1 - 1;
-      open_st = uniform(boundary(open_k, offsets, k0, k1, soff));
+      open_st = cnt < 64 ? window_uniform(vwin, open_k, k0) : uniform(boundary(open_k, offsets, k0, k1, soff));
       open_d = kNoneRel;
       if (tile_bad) {
         const int r = first_bit(regm, nz, (int)(open_st - ts), kTile);
