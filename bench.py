@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--no-copy", action="store_true", help="skip the fused copy + validate part")
     ap.add_argument("--no-latency", action="store_true", help="skip the 1 MiB latency part")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper-shaped random inputs")
     ap.add_argument("--serve-loads", default="10000,50000,200000", help="offered loads, requests/s")
     ap.add_argument("--serve-requests", type=int, default=100_000, help="measured requests per load")
     ap.add_argument("--serve-baseline-requests", type=int, default=20_000,
@@ -117,6 +118,10 @@ def main():
     # ---- heavy-tail batches: 20,000 Pareto strings, ~125 MiB and ~4 GiB ------------------------
     if not args.no_batch and not args.no_heavy:
         result["batched_heavy_tail"] = bench_heavy(u8, lib, synth, torch, dev, stream, sh, args)
+
+    # ---- the paper's randomized inputs: 65,536 strings of 16 KiB per byte-length mix ------------
+    if not args.no_batch and not args.no_paper:
+        result["paper_shaped"] = bench_paper_shaped(u8, lib, synth, torch, dev, stream, sh, args)
 
     # ---- serving: continuous batching under Poisson load vs one launch per request -----------
     if not args.no_serve:
@@ -613,6 +618,53 @@ def bench_heavy(u8, lib, synth, torch, dev, stream, sh, args):
         torch.cuda.empty_cache()
     u8.set_config(**saved)
     return rows
+
+
+def bench_paper_shaped(u8, lib, synth, torch, dev, stream, sh, args):
+    """The paper's randomized inputs (section 7.3): strings of 16 KiB whose code points have a
+    byte length uniform over {1}, {1,2}, {1,2,3} or {1,2,3,4}; 65,536 of them (1 GiB) per mix,
+    validated as one batch (each string its own stream, as each input is in the paper).  The
+    paper's single-core figures for these inputs are context only (other hardware, in-cache).
+    """
+    rows = []
+    n, length = 65536, 16384
+    flags = torch.empty(n, dtype=torch.uint8, device=dev)
+    ferr = torch.empty(n, dtype=torch.int64, device=dev)
+    for i, variant in enumerate(("unif1", "unif2", "unif3", "unif4")):
+        data, offsets, _ = synth.batch_from_lengths(np.full(n, length, np.int64), variant, 40 + i)
+        td = torch.from_numpy(data).to(dev)
+        to = torch.from_numpy(offsets).to(dev)
+        del data
+
+        def run():
+            rc = lib.utf8v_validate_batch_async(td.data_ptr(), to.data_ptr(), n, flags.data_ptr(),
+                                                ferr.data_ptr(), sh)
+            if rc:
+                raise u8.Utf8vError(rc, "utf8v_validate_batch_async")
+        ferr.fill_(-7)
+        t_w = time.perf_counter()
+        while time.perf_counter() - t_w < args.warmup_seconds:
+            run()
+            torch.cuda.synchronize()
+        if not bool((ferr == -1).all()):
+            raise SystemExit(f"wrong paper-shaped result ({variant})")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        blocks = []
+        for _ in range(3):
+            e0.record(stream)
+            for _ in range(5):
+                run()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            blocks.append(e0.elapsed_time(e1) * 1e-3 / 5)
+        t = float(np.median(blocks))
+        rows.append({"variant": variant, "ms": round(t * 1e3, 3), "GBps": round(n * length / t / 1e9, 1),
+                     "GiBps": round(n * length / t / 2**30, 1)})
+        log(f"paper-shaped {variant}: {rows[-1]['GBps']} GB/s")
+        del td, to
+        torch.cuda.empty_cache()
+    return {"workload": "65,536 strings x 16 KiB per byte-length mix (one batch, all valid)",
+            "results": rows}
 
 
 def bench_serving(synth, args):

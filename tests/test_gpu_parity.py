@@ -677,3 +677,19 @@ def test_batch_length_mix_far_from_stationary(u8):
                     assert np.array_equal(flags.cpu().numpy(), f_o), (name, err, waves)
     finally:
         u8.set_config(**old)
+
+
+@pytest.mark.gpu
+def test_batch_paper_randomized_inputs(u8):
+    """The paper's randomized inputs (section 7.3: code-point byte length uniform over {1},
+    {1,2}, {1,2,3}, {1,2,3,4}) as 16 KiB strings, some with an injected error, equal the oracle."""
+    for i, variant in enumerate(("unif1", "unif2", "unif3", "unif4")):
+        say(f"case: paper-shaped {variant}")
+        data, offsets, expected = synth.batch_from_lengths(np.full(512, 16384, np.int64), variant, 80 + i,
+                                                           err_frac=0.05)
+        f_o, e_o = oracle.first_error_batch(data, offsets)
+        assert np.array_equal(e_o[expected >= 0], expected[expected >= 0])
+        flags, ferr = u8.validate_batch(dev(data), dev(offsets))
+        torch.cuda.synchronize()
+        assert np.array_equal(ferr.cpu().numpy(), e_o), variant
+        assert np.array_equal(flags.cpu().numpy(), f_o), variant
