@@ -13,7 +13,8 @@
 //      batch (a padding string separates consecutive requests);
 //   3. the batch validator (one launch) runs over it;
 //   4. serve_scatter writes each request's flags and first-error offsets back
-//      into its pinned host result arrays;
+//      into its pinned host result arrays (a batch of one request has the
+//      validator write them there itself);
 //   5. an event marks the batch; the scheduler retires batches in order, stamps
 //      their requests done and releases their ring space.
 // A string's result depends only on its own bytes (each string is its own
@@ -316,14 +317,20 @@ bool utf8v_server::launch_batch_of(uint64_t first, uint64_t count) {
       e = hipGetLastError();
     }
   }
+  // A batch of one request (strings = the request's strings, in order) writes its results
+  // straight into the request's pinned host arrays: no scatter step after it.
+  const bool direct = count == 1;
   if (e == hipSuccess) {
     TuneBatch tb;
     utf8v_config c;
     utf8v_get_config(&c);
     tb.waves_per_cu = c.batch_waves_per_cu;
-    e = utf8v::launch_batch(batch_args(data, offs, plan.strings, flags, errs, wslots), tb, cus, st);
+    const Slot& s0 = slot(first);
+    e = utf8v::launch_batch(batch_args(data, offs, plan.strings, direct ? s0.flags : flags,
+                                       direct ? s0.errs : errs, wslots),
+                            tb, cus, st);
   }
-  if (e == hipSuccess && sblocks > 0) {
+  if (e == hipSuccess && sblocks > 0 && !direct) {
     if (inline_tables)
       hipLaunchKernelGGL(serve_scatter<InlineTables>, dim3((unsigned)sblocks), dim3(256), 0, st, it, (int)count,
                          flags, errs, plan.strings);
