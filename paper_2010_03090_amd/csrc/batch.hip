@@ -37,7 +37,8 @@ namespace utf8v {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kU = 4;                       // 1 KiB slabs per wave tile
+constexpr int kU = 4;                       // 1 KiB slabs per wave tile (one per byte lane of the plain check)
+static_assert(kU == 4, "the plain check transposes four slabs across the byte lanes");
 constexpr int kTile = kU * 1024;            // bytes per tile (one wave)
 constexpr int kMaskPad = 16;                // mask bytes kept before the tile (last 4 used)
 constexpr int kOffCap = 128;                // window boundaries cached in LDS for the error path
@@ -474,11 +475,8 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     }
     // bit u: this lane saw a plain error in slab u; bit 4 + u: a failed end check below reaches slab u
     uint32_t m = 0;
-    if (run) {
-#pragma unroll
-      for (int u = 0; u < kU; ++u)
-        m |= (chunk_errors(0u, x[u].x, x[u].y, x[u].z, x[u].w, prev[u]) != 0u ? 1u : 0u) << u;
-    }
+    if (run)  // byte lane u of the transposed check's result belongs to slab u
+      m = nonzero_bytes(chunks4_errors(0u, x[0], x[1], x[2], x[3], prev[0], prev[1], prev[2], prev[3]));
     // 5. the tile's bytes (and the 8 before it) in LDS, for the boundary checks, the per-string
     // recheck and the resolution
     const uint8_t* tile_bytes = sbytes + kMaskPad;  // tile_bytes[p - ts] = byte p, for p >= ts - 8

@@ -188,6 +188,87 @@ __device__ __forceinline__ uint32_t chunk_errors(uint32_t acc, uint32_t x0, uint
 }
 
 
+// ---- four streams across the byte lanes ------------------------------------------------
+// A tile gives each lane four 16-byte chunks, 1 KiB apart.  Transposed so that byte lane s
+// of register r_t holds byte t of chunk s, the byte before every byte of r_t is the same
+// byte lane of r_{t-1}: prev1 is the previous register itself, and the nibble indices and
+// sign masks of prev1 are those computed for r_{t-1} one step earlier, with no byte
+// alignment at all.
+
+// 4x4 byte transpose: r_k = byte k of a, b, c, d (in byte lanes 0..3).
+__device__ __forceinline__ void transpose4(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t& r0,
+                                           uint32_t& r1, uint32_t& r2, uint32_t& r3) {
+  const uint32_t t0 = perm(b, a, 0x05010400u);  // a0 b0 a1 b1
+  const uint32_t t1 = perm(d, c, 0x05010400u);  // c0 d0 c1 d1
+  const uint32_t t2 = perm(b, a, 0x07030602u);  // a2 b2 a3 b3
+  const uint32_t t3 = perm(d, c, 0x07030602u);  // c2 d2 c3 d3
+  r0 = perm(t1, t0, 0x05040100u);
+  r1 = perm(t1, t0, 0x07060302u);
+  r2 = perm(t3, t2, 0x05040100u);
+  r3 = perm(t3, t2, 0x07060302u);
+}
+
+// Values of the register before the current one (prev1), and must23's inputs.
+struct LaneCarry {
+  uint32_t neg, sh, sl, half;  // of r_{t-1}: sign mask, high-nibble and low-nibble indices, half selector
+  uint32_t f;                  // bit 7: r_{t-1} >= 0xF0
+  uint32_t g1, g2;             // g of r_{t-1} and r_{t-2} (bit 7: the byte >= 0xE0 or the byte before >= 0xF0)
+};
+
+__device__ __forceinline__ uint32_t sign_mask(uint32_t r) { return perm(r, r << 8, kSignSel); }
+
+// Carried values for a run that starts after the registers q1, q2, q3 (bytes t-3, t-2, t-1).
+__device__ __forceinline__ LaneCarry lanes_halo(uint32_t q1, uint32_t q2, uint32_t q3) {
+  LaneCarry c;
+  c.neg = sign_mask(q3);
+  c.sh = (q3 >> 4) & 0x07070707u;
+  c.sl = q3 & 0x07070707u;
+  c.half = low_half_selector(q3);
+  c.f = ge_mask7(q3, 0x10101010u);
+  c.g1 = or_and(ge_mask7(q3, 0x20202020u), ge_mask7(q2, 0x10101010u), 0x80808080u);
+  c.g2 = or_and(ge_mask7(q2, 0x20202020u), ge_mask7(q1, 0x10101010u), 0x80808080u);
+  return c;
+}
+
+// Errors of register r (sections 6.1-6.2), ORed into acc; c moves on to r.
+__device__ __forceinline__ uint32_t lanes_step(uint32_t acc, uint32_t r, LaneCarry& c) {
+  const uint32_t neg = sign_mask(r);
+  const uint32_t sh = (r >> 4) & 0x07070707u;
+  const uint32_t sc = lookup3(c.sh, c.sl, sh, c.neg, neg, c.half);
+  const uint32_t g = or_and(ge_mask7(r, 0x20202020u), c.f, 0x80808080u);
+  acc = or_xor(acc, sc, c.g2);  // must23 at t is g of t-2
+  c.g2 = c.g1;
+  c.g1 = g;
+  c.f = ge_mask7(r, 0x10101010u);
+  c.neg = neg;
+  c.sh = sh;
+  c.sl = r & 0x07070707u;
+  c.half = low_half_selector(r);
+  return acc;
+}
+
+// Errors of the four 16-byte chunks x0..x3 (each preceded by the dword p0..p3), ORed into
+// acc: the same decision as chunk_errors on each chunk.
+template <class V>
+__device__ __forceinline__ uint32_t chunks4_errors(uint32_t acc, const V& x0, const V& x1, const V& x2, const V& x3,
+                                                   uint32_t p0, uint32_t p1, uint32_t p2, uint32_t p3) {
+  uint32_t q0, q1, q2, q3;
+  transpose4(p0, p1, p2, p3, q0, q1, q2, q3);
+  LaneCarry c = lanes_halo(q1, q2, q3);
+  const uint32_t w[4][4] = {{x0.x, x1.x, x2.x, x3.x}, {x0.y, x1.y, x2.y, x3.y},
+                            {x0.z, x1.z, x2.z, x3.z}, {x0.w, x1.w, x2.w, x3.w}};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    uint32_t r0, r1, r2, r3;
+    transpose4(w[j][0], w[j][1], w[j][2], w[j][3], r0, r1, r2, r3);
+    acc = lanes_step(acc, r0, c);
+    acc = lanes_step(acc, r1, c);
+    acc = lanes_step(acc, r2, c);
+    acc = lanes_step(acc, r3, c);
+  }
+  return acc;
+}
+
 // ---- per-string masking (CSR batches) ----------------------------------------------------
 // s / sp: string-start masks (0xFF at positions where a string starts) of x and of the
 // dword before it.  Bytes of an earlier string count as zero (section 6: the stream

@@ -126,6 +126,11 @@ __device__ __forceinline__ void single_tile(const u32x4 (&x)[U], uint64_t base, 
     }
   }
   uint32_t acc = 0;
+  if (FULL && U % 4 == 0) {
+#pragma unroll
+    for (int u = 0; u < U; u += 4)
+      acc = chunks4_errors(acc, x[u], x[u + 1], x[u + 2], x[u + 3], prev[u], prev[u + 1], prev[u + 2], prev[u + 3]);
+  } else {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     if (FULL) {
@@ -134,6 +139,7 @@ __device__ __forceinline__ void single_tile(const u32x4 (&x)[U], uint64_t base, 
       const uint32_t e = chunk_errors(0u, x[u].x, x[u].y, x[u].z, x[u].w, prev[u]);
       acc |= (base + (uint64_t)u * 1024 + (uint64_t)lane * 16 < i1) ? e : 0u;
     }
+  }
   }
   if (__builtin_expect(acc != 0, 0) && dmin == kNone) {
     // first detection position of this lane (exact recomputation, rare)
