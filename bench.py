@@ -79,9 +79,9 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the validator shards by contiguous byte ranges with a 3-byte halo; see DESIGN.md)",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (a single buffer would shard "
+              "into contiguous byte ranges with a 3-byte halo and one minimum reduction; batches by "
+              "string ranges with no exchange)", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

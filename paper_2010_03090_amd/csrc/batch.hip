@@ -402,7 +402,7 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
   uint32_t carry = bm.w;    // the dword before the first tile
   uint32_t carry2 = bm.z;   // and the one before that
   const bool lane0 = lane == 0;
-  int ascii_skip = 0;
+  AsciiBackoff ascii;
   // the string open at the wave start (it began in an earlier wave) is found in the first window
   int64_t open_k = -2, open_st = 0, open_d = kNoneRel;
   // strings found valid in the previous tile, written during the next one (see step 2)
@@ -464,14 +464,12 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     carry2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)x[kU - 1].z, kDppWaveRor1, 0xF, 0xF, true);
     // 4. plain checks; a tile that is all ASCII with an ASCII halo cannot hold an error (6.4)
     bool run = true;
-    if (ascii_skip == 0) {
+    if (ascii.due()) {
       uint32_t o = 0;
 #pragma unroll
       for (int u = 0; u < kU; ++u) o |= x[u].x | x[u].y | x[u].z | x[u].w | prev[u];
       run = !__all((o & 0x80808080u) == 0);
-      if (run) ascii_skip = 3;
-    } else {
-      --ascii_skip;
+      ascii.result(!run);
     }
     // bit u: this lane saw a plain error in slab u; bit 4 + u: a failed end check below reaches slab u
     uint32_t m = 0;

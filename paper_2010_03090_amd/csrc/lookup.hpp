@@ -188,6 +188,30 @@ __device__ __forceinline__ uint32_t chunk_errors(uint32_t acc, uint32_t x0, uint
 }
 
 
+// ---- section 6.4's ASCII test, per tile ---------------------------------------------------
+// A tile whose bytes (and the three before it) are all ASCII cannot hold an error.  The test
+// is taken with an exponential back-off: after a tile that is not all ASCII it is skipped for
+// 3, 7, 15, ... up to 63 tiles, and a tile that is all ASCII brings it back to every tile.
+// Text without ASCII tiles pays for a handful of tests per wave, ASCII text skips every
+// tile, and mixed text is tested about as often as it has ASCII tiles.
+struct AsciiBackoff {
+  int skip = 0;  // tiles to go before the next test (wave-uniform)
+  int next = 3;  // skip after the next failed test
+  __device__ __forceinline__ bool due() {
+    if (skip == 0) return true;
+    --skip;
+    return false;
+  }
+  __device__ __forceinline__ void result(bool all_ascii) {
+    if (all_ascii) {
+      next = 3;
+    } else {
+      skip = next;
+      next = next < 63 ? 2 * next + 1 : 63;
+    }
+  }
+};
+
 // ---- four streams across the byte lanes ------------------------------------------------
 // A tile gives each lane four 16-byte chunks, 1 KiB apart.  Transposed so that byte lane s
 // of register r_t holds byte t of chunk s, the byte before every byte of r_t is the same

@@ -68,8 +68,6 @@ __device__ __forceinline__ uint32_t prev_dword(const SingleArgs& a, uint64_t pos
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kAsciiBackoff = 3;
-
 // Streaming 16-byte load; non-temporal, the input is read exactly once.
 __device__ __forceinline__ u32x4 load16(const uint8_t* p) {
   return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
@@ -100,7 +98,7 @@ __device__ __forceinline__ void store_tile(const u32x4 (&x)[U], uint8_t* __restr
 // before the tile and leaves with the tile's last dword.
 template <int U, bool ASCII, bool FULL>
 __device__ __forceinline__ void single_tile(const u32x4 (&x)[U], uint64_t base, uint64_t i1, int lane,
-                                            uint32_t& carry, uint64_t& dmin, int& ascii_skip) {
+                                            uint32_t& carry, uint64_t& dmin, AsciiBackoff& ascii) {
   // previous dword of each chunk: lane l-1's last dword (lane 0: lane 63 of the previous slab)
   uint32_t prev[U];
   const bool lane0 = lane == 0;
@@ -113,16 +111,13 @@ __device__ __forceinline__ void single_tile(const u32x4 (&x)[U], uint64_t base, 
   if (ASCII) {
     // Section 6.4: when the tile and the three bytes before it are all ASCII, no
     // check can fire in it (an ASCII byte after ASCII bytes is never an error).
-    // After a tile that is not all ASCII the wave skips the test for the next
-    // kAsciiBackoff tiles, so text without long ASCII runs barely pays for it.
-    if (ascii_skip == 0) {
+    if (ascii.due()) {
       uint32_t o = 0;
 #pragma unroll
       for (int u = 0; u < U; ++u) o |= x[u].x | x[u].y | x[u].z | x[u].w | prev[u];
-      if (__all((o & 0x80808080u) == 0)) return;
-      ascii_skip = kAsciiBackoff;
-    } else {
-      --ascii_skip;
+      const bool all_ascii = __all((o & 0x80808080u) == 0);
+      ascii.result(all_ascii);
+      if (all_ascii) return;
     }
   }
   uint32_t acc = 0;
@@ -261,7 +256,7 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
   const uint64_t t_end = t + a.tiles_per_wave < a.tiles ? t + a.tiles_per_wave : a.tiles;
   uint64_t dmin = kNone;
   if (t < t_end) {
-    int ascii_skip = 0;
+    AsciiBackoff ascii;
     uint32_t carry = prev_dword(a, a.i0 + t * W);
     // the buffer's last tile may be partial
     const uint64_t t_full = (t_end == a.tiles && a.i0 + a.tiles * W > a.i1) ? t_end - 1 : t_end;
@@ -272,14 +267,14 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
       for (; t + 1 < t_full; t += 2) {
         load_tile<U, true>(xb, a.buf, a.i0 + (t + 1) * W, a.i1, lane);
         if (COPY) store_tile<U, true>(xa, a.dst, a.i0 + t * W, a.i1, lane);
-        single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii_skip);
+        single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii);
         if (t + 2 < t_full) load_tile<U, true>(xa, a.buf, a.i0 + (t + 2) * W, a.i1, lane);
         if (COPY) store_tile<U, true>(xb, a.dst, a.i0 + (t + 1) * W, a.i1, lane);
-        single_tile<U, ASCII, true>(xb, a.i0 + (t + 1) * W, a.i1, lane, carry, dmin, ascii_skip);
+        single_tile<U, ASCII, true>(xb, a.i0 + (t + 1) * W, a.i1, lane, carry, dmin, ascii);
       }
       if (t < t_full) {
         if (COPY) store_tile<U, true>(xa, a.dst, a.i0 + t * W, a.i1, lane);
-        single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii_skip);
+        single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii);
         ++t;
       }
     }
@@ -287,7 +282,7 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
       u32x4 x[U];
       load_tile<U, false>(x, a.buf, a.i0 + t * W, a.i1, lane);
       if (COPY) store_tile<U, false>(x, a.dst, a.i0 + t * W, a.i1, lane);
-      single_tile<U, ASCII, false>(x, a.i0 + t * W, a.i1, lane, carry, dmin, ascii_skip);
+      single_tile<U, ASCII, false>(x, a.i0 + t * W, a.i1, lane, carry, dmin, ascii);
     }
   }
   dmin = edge < dmin ? edge : dmin;
