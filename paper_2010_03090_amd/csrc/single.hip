@@ -5,17 +5,20 @@
 // wave tiles of U KiB.  In a tile, slab u (1 KiB) is read by one
 // global_load_dwordx4 per lane (lane l reads bytes 16*l .. 16*l+15 of the slab),
 // so every load instruction of a wave covers 1 KiB of consecutive bytes.  The
-// up-to-15-byte head and tail outside the interior are validated by the
-// finalize kernel, with the bytes outside the buffer read as zero.
+// up-to-15-byte head and tail outside the interior are validated by the last
+// wave, with the bytes outside the buffer read as zero.
 //
 // The three bytes before each 16-byte chunk (the paper's previous register,
 // section 6.1) come from the neighbouring lane through DPP (wave_ror:1); lane 0
 // takes the last dword of the previous slab, and the first slab of a wave's
 // first tile reads it from memory (zero before the buffer start, section 6).
-// Inside a chunk the four dwords form a run: sign masks, nibble indices and the
-// section 6.2 inputs of one dword are shifted into the next (errors_next).
+// In a full tile a lane's four chunks are transposed across the byte lanes of
+// its registers (chunks4_errors), so the byte before each byte sits in the
+// previous register; in a partial tile the four dwords of each chunk form a run
+// whose sign masks, nibble indices and section 6.2 inputs are shifted from one
+// dword into the next (errors_next).
 //
-// Errors are ORed into a per-lane register (section 6, "error register").  Only
+// Errors are ORed into a per-lane register (the paper's error register).  Only
 // when it is non-zero does a lane recompute its chunk to find its first
 // detection position.  Each wave then reports its minimum and its arrival in a
 // 64-bit state word (arrivals in the high bits, least position in the low 40
