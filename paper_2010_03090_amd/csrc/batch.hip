@@ -83,6 +83,22 @@ __device__ __forceinline__ int64_t logical_wave(int64_t b, int64_t g) {
   return g % kXcds ? b : (b % kXcds) * (g / kXcds) + b / kXcds;
 }
 
+// A SIMD issues from its oldest ready wave first.  The loop below is bound by
+// instruction issue, so without help the oldest of a SIMD's waves runs ahead, the
+// youngest lags, and it finishes its last tiles nearly alone.  When every wave of the
+// grid is resident at once, a wave's priority falls as it gets through its tiles (3 for
+// the first quarter, then 2, 1, 0), so the waves of a SIMD keep pace with each other and
+// finish together.  (With more waves than fit, a wave that starts late would take the
+// SIMD from the waves finishing before it, so the levels are left off.)
+__device__ __forceinline__ void set_priority(int p) {
+  switch (p) {  // s_setprio takes an immediate
+    case 3: __builtin_amdgcn_s_setprio(3); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    default: __builtin_amdgcn_s_setprio(0); break;
+  }
+}
+
 // Wave-uniform 64-bit value kept in scalar registers.
 __device__ __forceinline__ int64_t uniform(int64_t v) {
   const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -368,7 +384,7 @@ __device__ __forceinline__ uint32_t bits_to_bytes(uint32_t nib) { return ((nib *
 // or a position b..b+2 of a failed check are checked again per string (a string-start
 // bitmap in LDS, the bytes of other strings masked to zero); the remaining slabs have
 // no error under either form.
-__global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* pa) {
+__global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* pa, int level) {
   const DevArgs a = args_of(a0, pa);
   __shared__ __align__(16) uint8_t sbytes[kTile + kMaskPad];  // tile positions [-16, kTile)
   __shared__ uint32_t sbits[kMaskWords + 1];                   // string starts at positions [-32, kTile)
@@ -408,7 +424,13 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
   // strings found valid in the previous tile, written during the next one (see step 2)
   int64_t pend_lo = 0, pend_hi = 0;
 
+  const int64_t t_first = t, t_count = t_end - t;
+  int prio = -1;
   for (; t < t_end; ++t) {
+    if (level) {
+      const int p = 3 - (int)((t - t_first) * 4 / t_count);
+      if (p != prio) set_priority(prio = p);
+    }
     const int64_t ts = c0 + t * kTile;
     const int64_t te = ts + kTile;
     // 1. boundaries of the window [ts-4, te): [k0, k1), those in [ts, te): [kb, k1).  A tile
@@ -690,8 +712,14 @@ BatchArgs batch_args(const uint8_t* data, const int64_t* offsets, int64_t n, uin
 // serves any batch); pa (device) overrides a when not null.
 static hipError_t launch_batch_kernels(const BatchArgs& a, const BatchArgs* pa, const TuneBatch& cfg, int num_cus,
                                        hipStream_t st) {
-  const int waves = num_cus * (cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1);
-  hipLaunchKernelGGL(batch_main, dim3(waves), dim3(64), 0, st, a, pa);
+  // one-wave workgroups of batch_main that a CU holds at once (its registers decide)
+  static const int resident = [] {
+    int blocks = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_main, 64, 0) == hipSuccess ? blocks : 0;
+  }();
+  const int per_cu = cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1;
+  const int waves = num_cus * per_cu;
+  hipLaunchKernelGGL(batch_main, dim3(waves), dim3(64), 0, st, a, pa, per_cu <= resident ? 1 : 0);
   return hipGetLastError();
 }
 
