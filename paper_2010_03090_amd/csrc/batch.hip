@@ -231,6 +231,13 @@ __device__ __forceinline__ void batch_mask(u32x4 (&x)[kU], int64_t ts, int64_t l
 
 constexpr int kMaskWords = kTile / 32;       // words of one per-position error bitmap
 
+// Bits q in [a, b) of a 16-bit chunk mask (a and b are clamped to [0, 16]).
+__device__ __forceinline__ uint32_t bit_range(int64_t a, int64_t b) {
+  const uint32_t lo = (uint32_t)(a < 0 ? 0 : (a > 16 ? 16 : a));
+  const uint32_t hi = (uint32_t)(b < 0 ? 0 : (b > 16 ? 16 : b));
+  return hi > lo ? ((1u << hi) - 1u) & ~((1u << lo) - 1u) : 0u;
+}
+
 __device__ __forceinline__ bool bit_at(const uint32_t* m, int r) { return (m[r >> 5] >> (r & 31)) & 1u; }
 
 // Which words of a bitmap hold a set bit: bit w of (nz.lo | nz.hi << 64).  Wave-uniform.
@@ -414,7 +421,7 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
   int64_t v;
   int64_t k0 = uniform(wave_window(offsets, n, lo, hi, wave_lo - 4, lane, v));
   batch_mask(x, wave_lo, lo, hi, lane);
-  const u32x4 bm = edge_mask(before, wave_lo - 16, lo, hi);
+  const u32x4 bm = wave_lo - 16 >= lo && wave_lo <= hi ? before : edge_mask(before, wave_lo - 16, lo, hi);
   uint32_t carry = bm.w;    // the dword before the first tile
   uint32_t carry2 = bm.z;   // and the one before that
   const bool lane0 = lane == 0;
@@ -424,12 +431,18 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
   // strings found valid in the previous tile, written during the next one (see step 2)
   int64_t pend_lo = 0, pend_hi = 0;
 
+  // priority 3 - k from the tile ceil(k * count / 4) tiles into the wave's run
   const int64_t t_first = t, t_count = t_end - t;
-  int prio = -1;
+  int prio = 3;
+  int64_t t_next = t_first + (t_count + 3) / 4;
+  if (level) set_priority(3);
   for (; t < t_end; ++t) {
-    if (level) {
-      const int p = 3 - (int)((t - t_first) * 4 / t_count);
-      if (p != prio) set_priority(prio = p);
+    if (level && t >= t_next) {
+      do {
+        --prio;
+        t_next = prio > 0 ? t_first + ((4 - prio) * t_count + 3) / 4 : INT64_MAX;
+      } while (t >= t_next);
+      set_priority(prio);
     }
     const int64_t ts = c0 + t * kTile;
     const int64_t te = ts + kTile;
@@ -584,11 +597,9 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
         if ((rbits | ebits) != 0u) {
           const int64_t base = ts + u * 1024 + lane * 16;
           if (base - 1 < lo || base + 16 > hi) {  // chunk at an edge of the batch range
-            for (int q = 0; q < 16; ++q) {
-              const int64_t pos = base + q;
-              if (!(pos >= lo && pos < hi)) rbits &= ~(1u << q);
-              if (!(pos - 1 >= lo && pos <= hi)) ebits &= ~(1u << q);
-            }
+            // regular bits only at positions in [lo, hi), end-check bits in [lo + 1, hi]
+            rbits &= bit_range(lo - base, hi - base);
+            ebits &= bit_range(lo + 1 - base, hi + 1 - base);
           }
           reinterpret_cast<uint16_t*>(regm)[u * 64 + lane] = (uint16_t)rbits;
           reinterpret_cast<uint16_t*>(endm)[u * 64 + lane] = (uint16_t)ebits;

@@ -630,6 +630,35 @@ def test_batch_exhaustive_short_strings_at_shifted_alignments(u8):
         assert np.array_equal(flags.cpu().numpy(), f_o), k
 
 
+def test_batch_subrange_with_invalid_bytes_around(u8):
+    """A batch over [lo, hi) of a larger buffer whose bytes outside the range would change the
+    results if read: lead bytes before lo, continuation bytes after hi that complete a truncated
+    last string.  Errors at the first and last bytes of the range, both edges at many offsets
+    against 16-byte chunks and 4 KiB tiles."""
+    rng = np.random.default_rng(31)
+    alphabet = np.array([0x41, 0x80, 0xA0, 0xBF, 0xC2, 0xE0, 0xE2, 0xED, 0xF0, 0xF4, 0xFF], np.uint8)
+    cases = 0
+    for pre in (1, 2, 3, 15, 16, 17, 1023, 4093, 4097):
+        for body_len in (1, 2, 3, 14, 17, 300, 4096 + 5):
+            say(f"case: sub-range pre {pre} body {body_len}")
+            body = alphabet[rng.integers(0, alphabet.size, body_len)]
+            # the last string ends in a truncated 3-byte sequence; bytes after hi complete it
+            tail = np.array([0xE2, 0x82], np.uint8)
+            body = np.concatenate([body, tail])
+            cuts = np.sort(rng.choice(np.arange(1, body.size), min(body.size - 1, 12), replace=False))
+            rel = np.unique(np.concatenate([[0], cuts, [body.size - 2], [body.size]]))
+            data = np.concatenate([np.full(pre, 0xF0, np.uint8), body, np.array([0xAC, 0x80, 0x80], np.uint8)])
+            offsets = (rel + pre).astype(np.int64)
+            f_o, e_o = oracle.first_error_batch(data, offsets)
+            assert f_o[-1] == 0   # the truncated last string is invalid on its own
+            flags, ferr = u8.validate_batch(dev(data), dev(offsets))
+            torch.cuda.synchronize()
+            assert np.array_equal(ferr.cpu().numpy(), e_o), (pre, body_len)
+            assert np.array_equal(flags.cpu().numpy(), f_o), (pre, body_len)
+            cases += 1
+    assert cases == 63
+
+
 def test_batch_boundary_alphabet_length_4_and_5(u8):
     """All strings of length 4 and 5 over the 27 boundary bytes of the byte-range table."""
     alpha = np.array([0x00, 0x41, 0x7F, 0x80, 0x8F, 0x90, 0x9F, 0xA0, 0xBF, 0xC0, 0xC1, 0xC2, 0xDF, 0xE0,
