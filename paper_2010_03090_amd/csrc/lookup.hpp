@@ -188,6 +188,26 @@ __device__ __forceinline__ uint32_t chunk_errors(uint32_t acc, uint32_t x0, uint
 }
 
 
+// ---- text of 1- and 2-byte characters -----------------------------------------------------
+// Where no byte of a position's window (the byte and the three before it) is >= 0xE0, the
+// checks of 6.1-6.2 can only report a continuation byte that does not follow a lead
+// (C0..DF), a lead that is not followed by a continuation, or a continuation after the
+// overlong leads C0 and C1; must23 is zero.  The same positions are then non-zero in
+//   (lead(prev1) ^ cont(byte)) | (prev1 is C0 or C1)
+// (bit 7 of each byte; the other bits are left over from the comparisons).
+
+// Bit 7 of each byte: the byte is >= 0xE0.
+__device__ __forceinline__ uint32_t ge_e0(uint32_t v) { return ge_mask7(v, 0x20202020u); }
+
+// Errors of register x preceded by register p (no byte >= 0xE0 in either): bit 7 of each
+// byte marks an error at that position.
+__device__ __forceinline__ uint32_t two_byte_errors(uint32_t x, uint32_t p) {
+  const uint32_t prev1 = align(x, p, 3);
+  const uint32_t lead = ge_mask7(prev1, 0x40404040u);                                 // prev1 >= 0xC0
+  const uint32_t t = UTF8V_BITOP3(x, ge_mask7(x, 0x40404040u), lead, (a & ~b) ^ c);  // cont(x) ^ lead
+  return UTF8V_BITOP3(t, lead, ge_mask7(prev1, 0x3E3E3E3Eu), a | (b & ~c));          // | prev1 in C0..C1
+}
+
 // ---- section 6.4's ASCII test, per tile ---------------------------------------------------
 // A tile whose bytes (and the three before it) are all ASCII cannot hold an error.  The test
 // is taken with an exponential back-off: after a tile that is not all ASCII it is skipped for

@@ -101,7 +101,8 @@ __device__ __forceinline__ void store_tile(const u32x4 (&x)[U], uint8_t* __restr
 // before the tile and leaves with the tile's last dword.
 template <int U, bool ASCII, bool FULL>
 __device__ __forceinline__ void single_tile(const u32x4 (&x)[U], uint64_t base, uint64_t i1, int lane,
-                                            uint32_t& carry, uint64_t& dmin, AsciiBackoff& ascii) {
+                                            uint32_t& carry, uint64_t& dmin, AsciiBackoff& ascii,
+                                            AsciiBackoff& two) {
   // previous dword of each chunk: lane l-1's last dword (lane 0: lane 63 of the previous slab)
   uint32_t prev[U];
   const bool lane0 = lane == 0;
@@ -125,9 +126,29 @@ __device__ __forceinline__ void single_tile(const u32x4 (&x)[U], uint64_t base, 
   }
   uint32_t acc = 0;
   if (FULL && U % 4 == 0) {
+    // a tile of 1- and 2-byte characters only (no byte >= 0xE0 in it or before its
+    // chunks) takes the short form of the checks; tested with the same back-off
+    bool short_form = false;
+    if (two.due()) {
+      uint32_t o = 0;
 #pragma unroll
-    for (int u = 0; u < U; u += 4)
-      acc = chunks4_errors(acc, x[u], x[u + 1], x[u + 2], x[u + 3], prev[u], prev[u + 1], prev[u + 2], prev[u + 3]);
+      for (int u = 0; u < U; ++u) o |= ge_e0(x[u].x) | ge_e0(x[u].y) | ge_e0(x[u].z) | ge_e0(x[u].w) | ge_e0(prev[u]);
+      short_form = __all((o & 0x80808080u) == 0);
+      two.result(short_form);
+    }
+    if (short_form) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        acc |= two_byte_errors(x[u].x, prev[u]) | two_byte_errors(x[u].y, x[u].x);
+        acc |= two_byte_errors(x[u].z, x[u].y) | two_byte_errors(x[u].w, x[u].z);
+      }
+      acc &= 0x80808080u;
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; u += 4)
+        acc = chunks4_errors(acc, x[u], x[u + 1], x[u + 2], x[u + 3], prev[u], prev[u + 1], prev[u + 2],
+                             prev[u + 3]);
+    }
   } else {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -259,7 +280,7 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
   const uint64_t t_end = t + a.tiles_per_wave < a.tiles ? t + a.tiles_per_wave : a.tiles;
   uint64_t dmin = kNone;
   if (t < t_end) {
-    AsciiBackoff ascii;
+    AsciiBackoff ascii, two;
     uint32_t carry = prev_dword(a, a.i0 + t * W);
     // the buffer's last tile may be partial
     const uint64_t t_full = (t_end == a.tiles && a.i0 + a.tiles * W > a.i1) ? t_end - 1 : t_end;
@@ -270,14 +291,14 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
       for (; t + 1 < t_full; t += 2) {
         load_tile<U, true>(xb, a.buf, a.i0 + (t + 1) * W, a.i1, lane);
         if (COPY) store_tile<U, true>(xa, a.dst, a.i0 + t * W, a.i1, lane);
-        single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii);
+        single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii, two);
         if (t + 2 < t_full) load_tile<U, true>(xa, a.buf, a.i0 + (t + 2) * W, a.i1, lane);
         if (COPY) store_tile<U, true>(xb, a.dst, a.i0 + (t + 1) * W, a.i1, lane);
-        single_tile<U, ASCII, true>(xb, a.i0 + (t + 1) * W, a.i1, lane, carry, dmin, ascii);
+        single_tile<U, ASCII, true>(xb, a.i0 + (t + 1) * W, a.i1, lane, carry, dmin, ascii, two);
       }
       if (t < t_full) {
         if (COPY) store_tile<U, true>(xa, a.dst, a.i0 + t * W, a.i1, lane);
-        single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii);
+        single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii, two);
         ++t;
       }
     }
@@ -285,7 +306,7 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
       u32x4 x[U];
       load_tile<U, false>(x, a.buf, a.i0 + t * W, a.i1, lane);
       if (COPY) store_tile<U, false>(x, a.dst, a.i0 + t * W, a.i1, lane);
-      single_tile<U, ASCII, false>(x, a.i0 + t * W, a.i1, lane, carry, dmin, ascii);
+      single_tile<U, ASCII, false>(x, a.i0 + t * W, a.i1, lane, carry, dmin, ascii, two);
     }
   }
   dmin = edge < dmin ? edge : dmin;

@@ -121,6 +121,34 @@ def test_single_error_at_every_offset_and_alignment(u8):
     say(f"checked {checked} single-error buffers")
 
 
+def test_two_byte_text_with_longer_characters_at_chunk_edges(u8):
+    """Text of 1- and 2-byte characters takes a short form of the checks per tile; a byte
+    >= 0xE0 in a chunk or in the three bytes before it must send the tile to the full
+    checks.  A 3- or 4-byte character (valid, or cut short) is placed across each chunk,
+    slab and tile edge of 2-byte text, at every split."""
+    n = 40 * 1024
+    base = np.full(n, 0x61, np.uint8)
+    base[5::37], base[6::37] = 0xC3, 0xA9          # U+00E9 every 37 bytes
+    edges = [16 * k for k in range(1, 6)] + [1024, 2048, 3072, 4096, 8192, 12288, 20480 + 16]
+    chars = [np.array(c, np.uint8) for c in ((0xE2, 0x82, 0xAC), (0xF0, 0x9F, 0x98, 0x80), (0xE2, 0x82),
+                                             (0xF0, 0x9F, 0x98), (0xED, 0xA0, 0x80))]
+    big = dev(np.zeros(n + 16, np.uint8))
+    valid = 0
+    for e in edges:
+        for ch in chars:
+            for k in range(1, ch.size + 1):
+                buf = base.copy()
+                buf[e - k: e - k + ch.size] = ch
+                for shift in (0, 5):
+                    big[shift: shift + n].copy_(torch.from_numpy(buf))
+                    got = u8.first_error(big[shift: shift + n])
+                    exp = oracle.first_error(buf)
+                    assert got == exp, (e, ch.tolist(), k, shift, got, exp)
+                valid += exp == -1
+    assert valid > 20
+    say(f"checked {len(edges) * sum(c.size for c in chars) * 2} buffers, {valid} valid")
+
+
 def test_sizes_and_alignments_valid_and_random(u8):
     big = dev(np.zeros(70_000, np.uint8))
     sizes = list(range(0, 70)) + [1023, 1024, 1025, 4095, 4096, 4097, 16384 + 5, 65536 - 1, 65536 + 3]

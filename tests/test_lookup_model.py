@@ -156,3 +156,22 @@ def test_plain_and_per_string_checks_agree_after_a_complete_character():
     for i in range(0, complete.shape[0], 512):
         assert agree(complete[i:i + 512]).all()
     assert not agree(tri[open_at_b][::97]).all()
+
+
+def test_short_form_for_text_without_bytes_from_e0():
+    """Where a position and the three bytes before it are all below 0xE0 (1- and 2-byte
+    characters only), the lookup checks (6.1-6.2) are non-zero exactly where a continuation
+    byte does not follow a lead, a lead is not followed by a continuation, or the lead
+    before is C0 or C1.  The GPU kernels take this short form for such tiles; here it is
+    checked against the lookup model over every (byte before, byte) pair below 0xE0,
+    with every choice of the two bytes before those from a set covering each range."""
+    p, c = np.meshgrid(np.arange(0xE0, dtype=np.uint8), np.arange(0xE0, dtype=np.uint8), indexing="ij")
+    p, c = p.reshape(-1), c.reshape(-1)
+    lead = p >= 0xC0
+    cont = (c >= 0x80) & (c < 0xC0)
+    short = (lead != cont) | (p == 0xC0) | (p == 0xC1)
+    for b3 in (0x00, 0x41, 0x80, 0xBF, 0xC2, 0xDF):
+        for b2 in (0x00, 0x41, 0x80, 0xBF, 0xC0, 0xDF):
+            window = np.stack([np.full_like(p, b3), np.full_like(p, b2), p, c], axis=1)
+            full = lm.position_errors(window)[:, 3] != 0
+            assert np.array_equal(full, short), (hex(b3), hex(b2))
