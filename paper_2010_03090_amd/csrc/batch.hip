@@ -391,7 +391,12 @@ __device__ __forceinline__ uint32_t bits_to_bytes(uint32_t nib) { return ((nib *
 // or a position b..b+2 of a failed check are checked again per string (a string-start
 // bitmap in LDS, the bytes of other strings masked to zero); the remaining slabs have
 // no error under either form.
-__global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* pa, int level) {
+// Five waves per SIMD: the kernel fits 96 VGPRs (93, no scratch); left to itself the
+// compiler takes 99 and four waves, which costs the resident-grid launches their
+// priority levels.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void batch_main(BatchArgs a0,
+                                                                                        const BatchArgs* pa,
+                                                                                        int level) {
   const DevArgs a = args_of(a0, pa);
   __shared__ __align__(16) uint8_t sbytes[kTile + kMaskPad];  // tile positions [-16, kTile)
   __shared__ uint32_t sbits[kMaskWords + 1];                   // string starts at positions [-32, kTile)
@@ -426,6 +431,9 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
   uint32_t carry2 = bm.z;   // and the one before that
   const bool lane0 = lane == 0;
   AsciiBackoff ascii;
+  // the short form for 1- and 2-byte text, first tested on the wave's fourth tile: a wave
+  // of a batch of short mixed strings has few tiles and would pay for a test in half of them
+  AsciiBackoff two{3, 7};
   // the string open at the wave start (it began in an earlier wave) is found in the first window
   int64_t open_k = -2, open_st = 0, open_d = kNoneRel;
   // strings found valid in the previous tile, written during the next one (see step 2)
@@ -508,8 +516,28 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, const BatchArgs* 
     }
     // bit u: this lane saw a plain error in slab u; bit 4 + u: a failed end check below reaches slab u
     uint32_t m = 0;
-    if (run)  // byte lane u of the transposed check's result belongs to slab u
-      m = nonzero_bytes(chunks4_errors(0u, x[0], x[1], x[2], x[3], prev[0], prev[1], prev[2], prev[3]));
+    if (run) {
+      // a tile without bytes >= 0xE0 (nor in the dword before each chunk) takes the short
+      // form of the checks: the same positions are non-zero
+      bool short_form = false;
+      if (two.due()) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) o |= ge_e0(x[u].x) | ge_e0(x[u].y) | ge_e0(x[u].z) | ge_e0(x[u].w) | ge_e0(prev[u]);
+        short_form = __all((o & 0x80808080u) == 0);
+        two.result(short_form);
+      }
+      if (short_form) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const uint32_t e = two_byte_errors(x[u].x, prev[u]) | two_byte_errors(x[u].y, x[u].x) |
+                             two_byte_errors(x[u].z, x[u].y) | two_byte_errors(x[u].w, x[u].z);
+          m |= (e & 0x80808080u) ? 1u << u : 0u;
+        }
+      } else {  // byte lane u of the transposed check's result belongs to slab u
+        m = nonzero_bytes(chunks4_errors(0u, x[0], x[1], x[2], x[3], prev[0], prev[1], prev[2], prev[3]));
+      }
+    }
     // 5. the tile's bytes (and the 8 before it) in LDS, for the boundary checks, the per-string
     // recheck and the resolution
     const uint8_t* tile_bytes = sbytes + kMaskPad;  // tile_bytes[p - ts] = byte p, for p >= ts - 8

@@ -687,6 +687,38 @@ def test_batch_subrange_with_invalid_bytes_around(u8):
     assert cases == 63
 
 
+def test_batch_two_byte_text_with_longer_characters_and_errors(u8):
+    """Batches of 1- and 2-byte text take a short form of the plain checks per tile; a byte
+    >= 0xE0 in a tile or in the three bytes before a chunk must send the tile to the full
+    checks.  Pieces are placed across chunk, slab and tile edges: 3- and 4-byte characters
+    (valid or cut short) in some trials, only 2-byte errors (a lone continuation, a lead
+    before ASCII, C0 or C1 leads, a lead at a string's end) in others; string boundaries
+    fall at, near and away from those edges."""
+    rng = np.random.default_rng(41)
+    n = 48 * 1024
+    base = np.full(n, 0x61, np.uint8)
+    base[5::37], base[6::37] = 0xC3, 0xA9          # U+00E9 every 37 bytes
+    edges = [16, 32, 1024, 2048, 4096, 8192, 12288, 16384 + 16, 20480 + 1024, 40960 + 48]
+    longer = [(0xE2, 0x82, 0xAC), (0xF0, 0x9F, 0x98, 0x80), (0xE2, 0x82), (0xF0, 0x9F, 0x98), (0xED, 0xA0, 0x80)]
+    short = [(0x80,), (0xC3, 0x41), (0xC0, 0x80), (0xC1, 0xBF), (0xC3,), (0xC3, 0xA9), (0xDF, 0xBF, 0xBF)]
+    for trial in range(8):
+        say(f"case: batch 2-byte text trial {trial}")
+        pieces = short if trial % 2 else short + longer
+        buf = base.copy()
+        for e in edges:
+            pc = np.array(pieces[rng.integers(len(pieces))], np.uint8)
+            k = int(rng.integers(1, pc.size + 1))
+            buf[e - k: e - k + pc.size] = pc
+        cuts = set(rng.integers(1, n, 60).tolist()) | {e + int(rng.integers(-3, 4)) for e in edges}
+        offsets = np.array(sorted({0, n} | {c for c in cuts if 0 < c < n}), np.int64)
+        f_o, e_o = oracle.first_error_batch(buf, offsets)
+        assert (f_o == 0).any() and (f_o == 1).any()
+        flags, ferr = u8.validate_batch(dev(buf), dev(offsets))
+        torch.cuda.synchronize()
+        assert np.array_equal(ferr.cpu().numpy(), e_o), trial
+        assert np.array_equal(flags.cpu().numpy(), f_o), trial
+
+
 def test_batch_boundary_alphabet_length_4_and_5(u8):
     """All strings of length 4 and 5 over the 27 boundary bytes of the byte-range table."""
     alpha = np.array([0x00, 0x41, 0x7F, 0x80, 0x8F, 0x90, 0x9F, 0xA0, 0xBF, 0xC0, 0xC1, 0xC2, 0xDF, 0xE0,
