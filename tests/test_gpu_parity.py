@@ -420,7 +420,7 @@ def test_stream_any_split_equals_whole(u8):
     """Chunked validation: every split (inside characters, empty and 1-byte chunks) equals the whole."""
     rng = np.random.default_rng(23)
     wholes = []
-    for v in ("mixed", "emoji", "cjk"):
+    for v in ("mixed", "emoji", "cjk", "latin"):   # latin: the short form, with leads carried across splits
         b = synth.text(200_003, v, 30)
         wholes.append(b.copy())
         for cls in range(7):
