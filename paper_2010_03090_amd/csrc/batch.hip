@@ -11,8 +11,8 @@
 // 64 MiB string and a million 64-byte strings load-balance alike.
 //
 // Per tile the wave first runs the single-buffer checks of section 6 over the tile as
-// plain text, and applies the end check of section 6.3 to the bytes before every
-// string boundary in it.  Where a boundary's end check passes, the string before it
+// plain text (in their short form where the tile holds no byte >= 0xE0), and applies
+// the end check of section 6.3 to the bytes before every string boundary in it.  Where a boundary's end check passes, the string before it
 // ends with a complete character, and then the checks at the boundary and the two
 // positions after it give the same verdict whether or not the bytes of the earlier
 // string are masked to zero; so a tile with neither a plain error nor a failed end

@@ -16,7 +16,10 @@
 // its registers (chunks4_errors), so the byte before each byte sits in the
 // previous register; in a partial tile the four dwords of each chunk form a run
 // whose sign masks, nibble indices and section 6.2 inputs are shifted from one
-// dword into the next (errors_next).
+// dword into the next (errors_next).  A full tile with no byte >= 0xE0 (nor in the
+// dword before each chunk) can only hold 1- and 2-byte characters; there the checks
+// reduce to a short form with the same error positions (two_byte_errors), tested
+// per tile with an exponential back-off.
 //
 // Errors are ORed into a per-lane register (the paper's error register).  Only
 // when it is non-zero does a lane recompute its chunk to find its first
