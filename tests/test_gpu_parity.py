@@ -784,3 +784,53 @@ def test_batch_paper_randomized_inputs(u8):
         torch.cuda.synchronize()
         assert np.array_equal(ferr.cpu().numpy(), e_o), variant
         assert np.array_equal(flags.cpu().numpy(), f_o), variant
+
+
+def test_randomized_shapes_against_the_oracle(u8):
+    """Seeded random single buffers (1- and 2-byte text most often, with random errors and a
+    stray 3- or 4-byte character), batches (mixed per-string variants, log-normal or Pareto
+    lengths, 0-50% errors, a prefix before offsets[0]) and chunked streams of 2-byte text."""
+    variants = ["latin", "ascii", "mixed", "cjk", "emoji", "latin", "latin"]
+    big = dev(np.zeros(2 * 2**20 + 64, np.uint8))
+    for it in range(60):
+        rng = np.random.default_rng(7000 + it)
+        kind = it % 3
+        say(f"case: randomized shape {it} kind {kind}")
+        if kind == 0:
+            n = int(rng.integers(1, 2 * 2**20))
+            b = synth.text(n, variants[int(rng.integers(len(variants)))], it)
+            for _ in range(int(rng.integers(0, 4))):
+                synth.inject_random(b, int(rng.integers(2**40)))
+            if rng.random() < 0.3 and n > 8:
+                ch = [(0xE2, 0x82, 0xAC), (0xF0, 0x9F, 0x98, 0x80), (0xED, 0x9F, 0xBF)][int(rng.integers(3))]
+                p = int(rng.integers(0, n - 4))
+                b[p:p + len(ch)] = ch
+            sh = int(rng.integers(0, 16))
+            big[sh: sh + n].copy_(torch.from_numpy(b))
+            assert u8.first_error(big[sh: sh + n]) == oracle.first_error(b), (it, n, sh)
+        elif kind == 1:
+            m = int(rng.integers(1, 20000))
+            dist = ["lognormal", "pareto"][int(rng.integers(2))]
+            lens = synth.lengths(m, dist, float(rng.choice([8, 64, 512])), 1.2 if dist == "lognormal" else 1.1,
+                                 0, 100000, it)
+            per = ([variants[int(i)] for i in rng.integers(0, len(variants), m)] if rng.random() < 0.5
+                   else variants[int(rng.integers(len(variants)))])
+            data, offsets, _ = synth.batch_from_lengths(lens, per, it, err_frac=float(rng.choice([0.0, 0.01, 0.1, 0.5])),
+                                                        base=int(rng.integers(0, 40)))
+            f_o, e_o = oracle.first_error_batch(data, offsets)
+            flags, ferr = u8.validate_batch(dev(data), dev(offsets))
+            torch.cuda.synchronize()
+            assert np.array_equal(ferr.cpu().numpy(), e_o), it
+            assert np.array_equal(flags.cpu().numpy(), f_o), it
+        else:
+            n = int(rng.integers(1, 2**20))
+            b = synth.text(n, "latin", it)
+            if rng.random() < 0.5:
+                synth.inject_random(b, int(rng.integers(2**40)))
+            td = dev(b)
+            cuts = np.sort(rng.integers(0, n + 1, int(rng.integers(1, 20))))
+            bounds = [0] + cuts.tolist() + [n]
+            with u8.Stream() as s:
+                for a, e in zip(bounds[:-1], bounds[1:]):
+                    s.update(td[a:e])
+                assert s.finish() == oracle.first_error(b), (it, n)
