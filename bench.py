@@ -286,6 +286,10 @@ def bench_single(u8, lib, synth, torch, dev, stream, sh, args):
         "read_ceiling_GBps": round(read_gbps, 1),
         "pct_of_read_ceiling": round(100 * value / read_gbps, 1),
         "per_variant_GBps": per_variant,
+        "per_variant_launch_us": {names[i]: {"min": round(float(per[:, i].min()) * 1e6, 1),
+                                             "median": round(float(np.median(per[:, i])) * 1e6, 1),
+                                             "mean": round(float(per[:, i].mean()) * 1e6, 1)}
+                                  for i in range(len(bufs))},
         "GiBps": round(total_bytes / wall / GIB, 1),
         "autotune": tuned,
     }
