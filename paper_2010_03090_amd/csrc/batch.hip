@@ -747,18 +747,23 @@ BatchArgs batch_args(const uint8_t* data, const int64_t* offsets, int64_t n, uin
   return a;
 }
 
-// One persistent grid of one-wave workgroups (fixed shape, so the same launch
-// serves any batch); pa (device) overrides a when not null.
-static hipError_t launch_batch_kernels(const BatchArgs& a, const BatchArgs* pa, const TuneBatch& cfg, int num_cus,
-                                       hipStream_t st) {
-  // one-wave workgroups of batch_main that a CU holds at once (its registers decide)
+// One-wave workgroups of batch_main that a CU holds at once (its registers decide);
+// asked once per process, and before any stream capture (see capture_batch_graph).
+static int resident_waves_per_cu() {
   static const int resident = [] {
     int blocks = 0;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_main, 64, 0) == hipSuccess ? blocks : 0;
   }();
+  return resident;
+}
+
+// One persistent grid of one-wave workgroups (fixed shape, so the same launch
+// serves any batch); pa (device) overrides a when not null.
+static hipError_t launch_batch_kernels(const BatchArgs& a, const BatchArgs* pa, const TuneBatch& cfg, int num_cus,
+                                       hipStream_t st) {
   const int per_cu = cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1;
   const int waves = num_cus * per_cu;
-  hipLaunchKernelGGL(batch_main, dim3(waves), dim3(64), 0, st, a, pa, per_cu <= resident ? 1 : 0);
+  hipLaunchKernelGGL(batch_main, dim3(waves), dim3(64), 0, st, a, pa, per_cu <= resident_waves_per_cu() ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -768,6 +773,7 @@ hipError_t launch_batch(const BatchArgs& a, const TuneBatch& cfg, int num_cus, h
 }
 
 hipError_t capture_batch_graph(const BatchArgs* dparams, const TuneBatch& cfg, int num_cus, hipGraphExec_t* exec) {
+  (void)resident_waves_per_cu();  // the occupancy query is not a call to make while capturing
   hipStream_t cap = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
   if (e != hipSuccess) return e;

@@ -3,6 +3,7 @@
 Bit-exact comparison of flags and first-error offsets (integer results, no
 tolerance).  Inputs are seeded and synthetic (paper_2010_03090_amd.synth).
 """
+import os
 import sys
 
 import numpy as np
@@ -14,6 +15,8 @@ from conftest import read_golden_rows, read_labelled_vectors
 from paper_2010_03090_amd import synth
 
 pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))  # the repository root
 
 torch = pytest.importorskip("torch")
 
@@ -343,6 +346,34 @@ def test_batch_graph_replays(u8):
         assert np.array_equal(ferr.cpu().numpy(), e_o)
     finally:
         u8.set_config(**old)
+
+
+def test_batch_graph_as_the_first_call_of_a_process(u8, tmp_path):
+    """A process whose first batch call is the captured-graph entry point (the launch
+    configuration's one-time queries then run before the capture): results equal the
+    oracle's.  Run in a child process, since this one has made batch calls already."""
+    import subprocess
+    data, offsets, _ = synth.lognormal_batch(5000, 31)
+    f_o, e_o = oracle.first_error_batch(data, offsets)
+    np.save(tmp_path / "data.npy", data)
+    np.save(tmp_path / "offsets.npy", offsets)
+    np.save(tmp_path / "expected.npy", e_o)
+    code = (
+        "import sys, numpy as np, torch\n"
+        f"sys.path.insert(0, {str(ROOT)!r})\n"
+        "import paper_2010_03090_amd as u8\n"
+        "u8.load()\n"
+        f"d = np.load({str(tmp_path / 'data.npy')!r}); o = np.load({str(tmp_path / 'offsets.npy')!r})\n"
+        f"e = np.load({str(tmp_path / 'expected.npy')!r})\n"
+        "td, to = torch.from_numpy(d).cuda(), torch.from_numpy(o).cuda()\n"
+        "flags = torch.empty(e.size, dtype=torch.uint8, device='cuda')\n"
+        "ferr = torch.full((e.size,), -9, dtype=torch.int64, device='cuda')\n"
+        "u8.validate_batch_graph(td, to, flags, ferr)\n"
+        "torch.cuda.synchronize()\n"
+        "assert np.array_equal(ferr.cpu().numpy(), e)\n"
+        "print('graph first call ok', flush=True)\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=100)
+    assert r.returncode == 0 and "graph first call ok" in r.stdout, r.stderr[-2000:]
 
 
 def test_tuning_invariance(u8):
