@@ -110,6 +110,7 @@ int workspace(hipStream_t st, Workspace** out) {
     e = hipMemcpy(w->dmin, init, sizeof init, hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) e = utf8v::launch_batch_slots_init(w->slot, slots, st);
+  if (e == hipSuccess) utf8v::batch_launch_queries();
   if (e != hipSuccess) {
     free_workspace(*w);
     return hip_fail(e);

@@ -748,7 +748,8 @@ BatchArgs batch_args(const uint8_t* data, const int64_t* offsets, int64_t n, uin
 }
 
 // One-wave workgroups of batch_main that a CU holds at once (its registers decide);
-// asked once per process, and before any stream capture (see capture_batch_graph).
+// asked once per process, when a stream's workspace is made and before the graph
+// form's capture, so never while a stream is being captured.
 static int resident_waves_per_cu() {
   static const int resident = [] {
     int blocks = 0;
@@ -772,8 +773,10 @@ hipError_t launch_batch(const BatchArgs& a, const TuneBatch& cfg, int num_cus, h
   return launch_batch_kernels(a, nullptr, cfg, num_cus, st);
 }
 
+void batch_launch_queries() { (void)resident_waves_per_cu(); }
+
 hipError_t capture_batch_graph(const BatchArgs* dparams, const TuneBatch& cfg, int num_cus, hipGraphExec_t* exec) {
-  (void)resident_waves_per_cu();  // the occupancy query is not a call to make while capturing
+  batch_launch_queries();  // the occupancy query is not a call to make while capturing
   hipStream_t cap = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
   if (e != hipSuccess) return e;

@@ -55,6 +55,7 @@ BatchArgs batch_args(const uint8_t* data, const int64_t* offsets, int64_t n, uin
                      unsigned long long* slot);
 hipError_t launch_batch(const BatchArgs& a, const TuneBatch& cfg, int num_cus, hipStream_t st);
 hipError_t launch_batch_slots_init(unsigned long long* slot, int slots, hipStream_t st);
+void batch_launch_queries();  // one-time queries of the batch launch, made outside any stream capture
 hipError_t capture_batch_graph(const BatchArgs* dparams, const TuneBatch& cfg, int num_cus, hipGraphExec_t* exec);
 hipError_t launch_offsets_check(const int64_t* offsets, int64_t n, int* bad, int num_cus, hipStream_t st);
 hipError_t launch_classify(const uint8_t* buf, uint64_t n, uint8_t* sc, uint8_t* err, hipStream_t st);
