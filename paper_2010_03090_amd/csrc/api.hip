@@ -18,7 +18,7 @@ thread_local int g_last_status = UTF8V_OK;
 thread_local int g_last_hip = 0;
 
 std::mutex g_mu;
-utf8v_config g_cfg = {4, 24, 1, 16, 1};
+utf8v_config g_cfg = {4, 20, 1, 16, 1};
 
 constexpr int kParamSlots = 64;
 constexpr int kBatchSlotsPerCu = 64;  // = the largest batch_waves_per_cu  // pinned parameter-block staging slots per stream (graph launches)
@@ -110,7 +110,10 @@ int workspace(hipStream_t st, Workspace** out) {
     e = hipMemcpy(w->dmin, init, sizeof init, hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) e = utf8v::launch_batch_slots_init(w->slot, slots, st);
-  if (e == hipSuccess) utf8v::batch_launch_queries();
+  if (e == hipSuccess) {
+    utf8v::batch_launch_queries();
+    utf8v::single_launch_queries();
+  }
   if (e != hipSuccess) {
     free_workspace(*w);
     return hip_fail(e);

@@ -83,22 +83,6 @@ __device__ __forceinline__ int64_t logical_wave(int64_t b, int64_t g) {
   return g % kXcds ? b : (b % kXcds) * (g / kXcds) + b / kXcds;
 }
 
-// A SIMD issues from its oldest ready wave first.  The loop below is bound by
-// instruction issue, so without help the oldest of a SIMD's waves runs ahead, the
-// youngest lags, and it finishes its last tiles nearly alone.  When every wave of the
-// grid is resident at once, a wave's priority falls as it gets through its tiles (3 for
-// the first quarter, then 2, 1, 0), so the waves of a SIMD keep pace with each other and
-// finish together.  (With more waves than fit, a wave that starts late would take the
-// SIMD from the waves finishing before it, so the levels are left off.)
-__device__ __forceinline__ void set_priority(int p) {
-  switch (p) {  // s_setprio takes an immediate
-    case 3: __builtin_amdgcn_s_setprio(3); break;
-    case 2: __builtin_amdgcn_s_setprio(2); break;
-    case 1: __builtin_amdgcn_s_setprio(1); break;
-    default: __builtin_amdgcn_s_setprio(0); break;
-  }
-}
-
 // Wave-uniform 64-bit value kept in scalar registers.
 __device__ __forceinline__ int64_t uniform(int64_t v) {
   const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -439,19 +423,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
   // strings found valid in the previous tile, written during the next one (see step 2)
   int64_t pend_lo = 0, pend_hi = 0;
 
-  // priority 3 - k from the tile ceil(k * count / 4) tiles into the wave's run
-  const int64_t t_first = t, t_count = t_end - t;
-  int prio = 3;
-  int64_t t_next = t_first + (t_count + 3) / 4;
-  if (level) set_priority(3);
+  PriorityLevels levels(level != 0, t, t_end - t);
   for (; t < t_end; ++t) {
-    if (level && t >= t_next) {
-      do {
-        --prio;
-        t_next = prio > 0 ? t_first + ((4 - prio) * t_count + 3) / 4 : INT64_MAX;
-      } while (t >= t_next);
-      set_priority(prio);
-    }
+    levels.step(t);
     const int64_t ts = c0 + t * kTile;
     const int64_t te = ts + kTile;
     // 1. boundaries of the window [ts-4, te): [k0, k1), those in [ts, te): [kb, k1).  A tile

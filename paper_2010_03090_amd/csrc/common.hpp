@@ -11,7 +11,7 @@ constexpr int kDppWaveRor1 = 0x13C;               // DPP wave_ror:1 -- lane l re
 
 struct TuneSingle {
   int unroll = 4;             // dwordx4 loads in flight per lane (1 KiB per wave each)
-  int waves_per_cu = 24;      // persistent waves per compute unit (large = one tile per wave)
+  int waves_per_cu = 20;      // persistent waves per compute unit (large = one tile per wave)
   int min_tiles_per_wave = 1;
   int ascii = 1;              // section 6.4 fast path for all-ASCII slabs
 };
@@ -55,7 +55,8 @@ BatchArgs batch_args(const uint8_t* data, const int64_t* offsets, int64_t n, uin
                      unsigned long long* slot);
 hipError_t launch_batch(const BatchArgs& a, const TuneBatch& cfg, int num_cus, hipStream_t st);
 hipError_t launch_batch_slots_init(unsigned long long* slot, int slots, hipStream_t st);
-void batch_launch_queries();  // one-time queries of the batch launch, made outside any stream capture
+void batch_launch_queries();   // one-time queries of the batch launch, made outside any stream capture
+void single_launch_queries();  // the same for the single-buffer launches
 hipError_t capture_batch_graph(const BatchArgs* dparams, const TuneBatch& cfg, int num_cus, hipGraphExec_t* exec);
 hipError_t launch_offsets_check(const int64_t* offsets, int64_t n, int* bad, int num_cus, hipStream_t st);
 hipError_t launch_classify(const uint8_t* buf, uint64_t n, uint8_t* sc, uint8_t* err, hipStream_t st);
@@ -66,5 +67,41 @@ hipError_t launch_error_classes(const uint8_t* data, const int64_t* offsets, int
                                 uint8_t* out, int num_cus, hipStream_t st);
 hipError_t launch_error_class_one(const uint8_t* buf, int64_t len, const int64_t* first_err, uint8_t* out,
                                   hipStream_t st);
+
+// A SIMD issues from its oldest ready wave first.  In a loop bound by instruction
+// issue the oldest of a SIMD's waves then runs ahead, the youngest lags, and it
+// finishes its last tiles nearly alone.  When every wave of the grid is resident at
+// once, the kernels lower a wave's priority as it gets through its tiles (3 for the
+// first quarter, then 2, 1, 0), so the waves of a SIMD keep pace with each other and
+// finish together.  (With more waves than fit, a wave that starts late would take the
+// SIMD from the waves finishing before it, so the levels are left off.)
+__device__ __forceinline__ void set_priority(int p) {
+  switch (p) {  // s_setprio takes an immediate
+    case 3: __builtin_amdgcn_s_setprio(3); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    default: __builtin_amdgcn_s_setprio(0); break;
+  }
+}
+
+// The priority levels of a run of `count` tiles from tile `first`: level 3 - k from the
+// tile ceil(k * count / 4) tiles into the run.  Wave-uniform; step() at each tile.
+struct PriorityLevels {
+  int64_t first, count, next;
+  int prio = 3;
+  bool on;
+  __device__ PriorityLevels(bool level, int64_t first_tile, int64_t tiles)
+      : first(first_tile), count(tiles), next(first_tile + (tiles + 3) / 4), on(level) {
+    if (on) set_priority(3);
+  }
+  __device__ __forceinline__ void step(int64_t t) {
+    if (!on || t < next) return;
+    do {
+      --prio;
+      next = prio > 0 ? first + ((4 - prio) * count + 3) / 4 : INT64_MAX;
+    } while (t >= next);
+    set_priority(prio);
+  }
+};
 
 }  // namespace utf8v

@@ -51,6 +51,7 @@ struct SingleArgs {
   int end_check;              // apply the section 6.3 end check at position n (else positions >= n do not exist)
   int keep_first;             // leave *out alone if it already holds an error; write no -1
   uint8_t* dst;               // copy the buffer here while validating it (the copying kernel only)
+  int level;                  // the whole grid is resident at once: priority levels (common.hpp)
 };
 
 // Byte at position p of a buffer whose history (positions -8..-1) is h; zero elsewhere.
@@ -264,7 +265,9 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
   __shared__ unsigned long long blk_min;  // least detection of the workgroup's waves so far
   __shared__ unsigned blk_done;           // waves of the workgroup that have finished
   const int lane = threadIdx.x & 63;
-  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  // wave index, held in a scalar register: the tile counters and priority levels below follow it
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) +
+                        (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
   const uint64_t W = (uint64_t)U * 1024;
   if (threadIdx.x == 0) {
@@ -291,7 +294,9 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
       // two register sets in turn: one is classified while the other's loads are in flight
       u32x4 xa[U], xb[U];
       load_tile<U, true>(xa, a.buf, a.i0 + t * W, a.i1, lane);
+      PriorityLevels levels(a.level != 0, t, t_full - t);
       for (; t + 1 < t_full; t += 2) {
+        levels.step(t);
         load_tile<U, true>(xb, a.buf, a.i0 + (t + 1) * W, a.i1, lane);
         if (COPY) store_tile<U, true>(xa, a.dst, a.i0 + t * W, a.i1, lane);
         single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii, two);
@@ -353,12 +358,45 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
 
 // ---- launch -----------------------------------------------------------------------------
 
+// Waves per CU of single_main<U, ASCII, COPY> resident at once (its registers decide).
+// Asked once per process, when a stream's workspace is made (single_launch_queries),
+// so never while a stream is being captured.
+template <int U, bool ASCII, bool COPY>
+static int resident_waves() {
+  static const int waves = [] {
+    int blocks = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, single_main<U, ASCII, COPY>, 256, 0) == hipSuccess
+               ? 4 * blocks
+               : 0;
+  }();
+  return waves;
+}
+
+template <int U>
+static void resident_waves_all() {
+  (void)resident_waves<U, true, true>();
+  (void)resident_waves<U, true, false>();
+  (void)resident_waves<U, false, true>();
+  (void)resident_waves<U, false, false>();
+}
+
+void single_launch_queries() {
+  resident_waves_all<1>();
+  resident_waves_all<2>();
+  resident_waves_all<4>();
+  resident_waves_all<8>();
+}
+
 template <int U, bool ASCII>
-static hipError_t launch_single_t(const SingleArgs& a, int grid, hipStream_t st) {
-  if (a.dst)
+static hipError_t launch_single_t(SingleArgs a, int grid, int num_cus, hipStream_t st) {
+  const int64_t waves = 4 * (int64_t)grid;
+  if (a.dst) {
+    a.level = waves <= (int64_t)num_cus * resident_waves<U, ASCII, true>() ? 1 : 0;
     hipLaunchKernelGGL((single_main<U, ASCII, true>), dim3(grid), dim3(256), 0, st, a);
-  else
+  } else {
+    a.level = waves <= (int64_t)num_cus * resident_waves<U, ASCII, false>() ? 1 : 0;
     hipLaunchKernelGGL((single_main<U, ASCII, false>), dim3(grid), dim3(256), 0, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -393,6 +431,7 @@ hipError_t launch_single_any(const uint8_t* buf, uint8_t* dst, uint64_t n, unsig
   a.buf = buf; a.n = n; a.i0 = i0; a.i1 = i1; a.state = state; a.out = out;
   a.hist = hist; a.base = base; a.end_check = end_check ? 1 : 0; a.keep_first = keep_first ? 1 : 0;
   a.dst = dst;
+  a.level = 0;
   a.tiles = i1 > i0 ? (i1 - i0 + W - 1) / W : 0;
   const uint64_t max_waves = (uint64_t)num_cus * (uint64_t)cfg.waves_per_cu;
   a.tiles_per_wave = (a.tiles + max_waves - 1) / max_waves;
@@ -401,10 +440,10 @@ hipError_t launch_single_any(const uint8_t* buf, uint8_t* dst, uint64_t n, unsig
   const int grid = (int)((waves + 3) / 4);  // at least one workgroup: it also does the edges and the result
   const bool asc = cfg.ascii != 0;
   switch (U) {
-    case 1: return asc ? launch_single_t<1, true>(a, grid, st) : launch_single_t<1, false>(a, grid, st);
-    case 2: return asc ? launch_single_t<2, true>(a, grid, st) : launch_single_t<2, false>(a, grid, st);
-    case 8: return asc ? launch_single_t<8, true>(a, grid, st) : launch_single_t<8, false>(a, grid, st);
-    default: return asc ? launch_single_t<4, true>(a, grid, st) : launch_single_t<4, false>(a, grid, st);
+    case 1: return asc ? launch_single_t<1, true>(a, grid, num_cus, st) : launch_single_t<1, false>(a, grid, num_cus, st);
+    case 2: return asc ? launch_single_t<2, true>(a, grid, num_cus, st) : launch_single_t<2, false>(a, grid, num_cus, st);
+    case 8: return asc ? launch_single_t<8, true>(a, grid, num_cus, st) : launch_single_t<8, false>(a, grid, num_cus, st);
+    default: return asc ? launch_single_t<4, true>(a, grid, num_cus, st) : launch_single_t<4, false>(a, grid, num_cus, st);
   }
 }
 
