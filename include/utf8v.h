@@ -284,7 +284,8 @@ int utf8v_serve_replay(const utf8v_server_config *cfg, int mode, const uint8_t *
 typedef struct {
   int32_t unroll;            /* single buffer: dwordx4 loads per lane per tile, 1, 2, 4 or 8 */
   int32_t waves_per_cu;      /* single buffer: persistent waves per compute unit, >= 1 */
-  int32_t ascii;             /* 1: skip classification of all-ASCII 1 KiB slabs (section 6.4) */
+  int32_t ascii;             /* 1: skip classification of all-ASCII wave tiles (section 6.4; tested per
+                                tile of `unroll` KiB, with an exponential back-off after a non-ASCII one) */
   int32_t batch_waves_per_cu; /* batch: persistent one-wave workgroups per compute unit, 1..64 */
   int32_t batch_ascii;       /* reserved (the batch kernel always uses the section 6.4 skip) */
 } utf8v_config;
