@@ -93,14 +93,13 @@ int utf8v_validate_batch_async(const uint8_t *data, const int64_t *offsets, int6
 
 /*
  * utf8v_validate_batch_graph -- as utf8v_validate_batch_async, launched as one
- * replay of a HIP graph (the persistent validation kernel) captured once per
- * (device, stream) and launch configuration.  The kernel reads its arguments
- * from a per-stream device parameter block; each call enqueues a 48-byte copy of
- * the new arguments (from one of 64 pinned staging slots) followed by the graph
- * launch, so any batch shape replays the same graph.  The first call on a stream
- * allocates the block and captures the graph (it must not run under stream
- * capture); later calls allocate nothing.  A 65th call in flight on one stream
- * waits for the first to have started.
+ * replay of a HIP graph holding the persistent validation kernel, made once per
+ * (device, stream) and launch configuration.  Each call sets the kernel node's
+ * arguments to this batch and launches the graph, so any batch shape replays the
+ * same graph; replays already enqueued keep their own arguments.  The call must
+ * not itself be made under stream capture (UTF8V_EINVAL): a capture would keep
+ * this call's arguments in the caller's graph.  To capture a batch validation,
+ * capture utf8v_validate_batch_async instead.
  */
 int utf8v_validate_batch_graph(const uint8_t *data, const int64_t *offsets, int64_t n,
                                uint8_t *out_flags, int64_t *out_first_err, void *stream);

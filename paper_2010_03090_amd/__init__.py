@@ -43,6 +43,37 @@ def _dev_u8(t, name="buf"):
     return t
 
 
+def _dev_tensor(t, dtype, n: int, device, name: str):
+    """t must be a contiguous CUDA tensor of `dtype` with at least n elements on `device`."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA {dtype} tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < n:
+        raise ValueError(f"{name} holds {t.numel()} elements, {n} are written")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the input on {device}")
+    return t
+
+
+def _batch_args(data, offsets, flags, first_err) -> int:
+    """Check a CSR batch call's tensors (all on one device); returns n."""
+    torch = _torch()
+    _dev_u8(data, "data")
+    if not isinstance(offsets, torch.Tensor) or offsets.dtype != torch.int64 or not offsets.is_cuda \
+            or offsets.numel() < 1:
+        raise TypeError("offsets must be a CUDA int64 tensor with n+1 entries")
+    if not offsets.is_contiguous():
+        raise ValueError("offsets must be contiguous")
+    if offsets.device != data.device:
+        raise ValueError(f"offsets is on {offsets.device}, data on {data.device}")
+    n = offsets.numel() - 1
+    _dev_tensor(flags, torch.uint8, n, data.device, "flags")
+    _dev_tensor(first_err, torch.int64, n, data.device, "first_err")
+    return n
+
+
 def first_error(buf, stream=None) -> int:
     """First-error offset of a CUDA uint8 tensor (-1 if it is valid UTF-8). Synchronizes the stream."""
     _dev_u8(buf)
@@ -61,18 +92,14 @@ def validate_async(buf, out, stream=None) -> None:
     """Enqueue validation; out (CUDA int64 tensor, 1 element) receives the first-error offset."""
     torch = _torch()
     _dev_u8(buf)
-    if out.dtype != torch.int64 or not out.is_cuda or out.numel() < 1:
-        raise TypeError("out must be a CUDA int64 tensor")
+    _dev_tensor(out, torch.int64, 1, buf.device, "out")
     check(load().utf8v_validate_async(buf.data_ptr() if buf.numel() else None, buf.numel(), out.data_ptr(),
                                       _stream_handle(stream)), "utf8v_validate_async")
 
 
 def validate_batch_async(data, offsets, flags, first_err, stream=None) -> None:
-    torch = _torch()
-    _dev_u8(data, "data")
-    n = offsets.numel() - 1
-    if offsets.dtype != torch.int64 or not offsets.is_cuda or n < 0:
-        raise TypeError("offsets must be a CUDA int64 tensor with n+1 entries")
+    """Enqueue the validation of CSR strings; flags (uint8) and first_err (int64) get n entries."""
+    n = _batch_args(data, offsets, flags, first_err)
     if n == 0:
         return
     check(load().utf8v_validate_batch_async(data.data_ptr() if data.numel() else offsets.data_ptr(),
@@ -82,11 +109,7 @@ def validate_batch_async(data, offsets, flags, first_err, stream=None) -> None:
 
 def validate_batch_graph(data, offsets, flags, first_err, stream=None) -> None:
     """As validate_batch_async, launched as one replay of the per-stream captured HIP graph."""
-    torch = _torch()
-    _dev_u8(data, "data")
-    n = offsets.numel() - 1
-    if offsets.dtype != torch.int64 or not offsets.is_cuda or n < 0:
-        raise TypeError("offsets must be a CUDA int64 tensor with n+1 entries")
+    n = _batch_args(data, offsets, flags, first_err)
     if n == 0:
         return
     check(load().utf8v_validate_batch_graph(data.data_ptr() if data.numel() else offsets.data_ptr(),
@@ -101,6 +124,7 @@ def validate_batch(data, offsets, stream=None):
     result tensors are ready when the given (or current) stream reaches them.
     """
     torch = _torch()
+    _dev_u8(data, "data")
     n = offsets.numel() - 1
     flags = torch.empty(max(n, 0), dtype=torch.uint8, device=offsets.device)
     ferr = torch.empty(max(n, 0), dtype=torch.int64, device=offsets.device)
@@ -119,6 +143,7 @@ def copy_validate(src, dst, out, stream=None) -> None:
     _dev_u8(dst, "dst")
     if dst.numel() < src.numel():
         raise ValueError("dst is smaller than src")
+    _dev_tensor(out, torch.int64, 1, dst.device, "out")
     check(load().utf8v_copy_validate(dst.data_ptr() if dst.numel() else None,
                                      src.data_ptr() if src.numel() else None, src.numel(), out.data_ptr(),
                                      _stream_handle(stream)), "utf8v_copy_validate")
@@ -145,6 +170,7 @@ def error_classes(data, offsets, first_err, stream=None):
     torch = _torch()
     n = offsets.numel() - 1
     out = torch.empty(max(n, 0), dtype=torch.uint8, device=offsets.device)
+    _batch_args(data, offsets, out, first_err)
     if n > 0:
         check(load().utf8v_error_classes(data.data_ptr() if data.numel() else offsets.data_ptr(),
                                          offsets.data_ptr(), n, first_err.data_ptr(), out.data_ptr(),
@@ -202,6 +228,9 @@ class Stream:
 
 
 def check_offsets(offsets, stream=None) -> bool:
+    """True iff offsets (CUDA int64, n+1 entries) is non-decreasing from a non-negative start."""
+    torch = _torch()
+    _dev_tensor(offsets, torch.int64, 1, None, "offsets")
     n = offsets.numel() - 1
     return bool(check(load().utf8v_check_offsets(offsets.data_ptr(), n, _stream_handle(stream)),
                       "utf8v_check_offsets"))

@@ -20,8 +20,7 @@ thread_local int g_last_hip = 0;
 std::mutex g_mu;
 utf8v_config g_cfg = {4, 20, 1, 16, 1};
 
-constexpr int kParamSlots = 64;
-constexpr int kBatchSlotsPerCu = 64;  // = the largest batch_waves_per_cu  // pinned parameter-block staging slots per stream (graph launches)
+constexpr int kBatchSlotsPerCu = 64;  // = the largest batch_waves_per_cu
 
 struct Workspace {
   unsigned long long* dmin = nullptr;  // device: scratch words (result, flag)
@@ -30,14 +29,11 @@ struct Workspace {
   int* flag = nullptr;                 // device: scratch flag (offset checks)
   int64_t* host = nullptr;             // pinned host copy of result / flag
   unsigned long long* slot = nullptr;  // device: batch cross-wave slots (self-cleaning), kBatchSlotsPerCu per CU
-  // graph-replayed batch launches
   std::mutex mu;
-  utf8v::BatchArgs* dparams = nullptr;  // device parameter block read by the captured kernels
-  utf8v::BatchArgs* hslots = nullptr;   // pinned staging slots for the block's contents
-  hipEvent_t slot_done[kParamSlots] = {};
-  bool slot_used[kParamSlots] = {};
-  int next_slot = 0;
+  // graph-replayed batch launches: a one-node graph whose arguments are set before each replay
+  hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipGraphNode_t node = nullptr;
   int graph_waves = 0, graph_cus = 0;
 };
 
@@ -72,10 +68,7 @@ int num_cus_of(int dev) {
 
 void free_workspace(Workspace& w) {
   if (w.exec) (void)hipGraphExecDestroy(w.exec);
-  for (int i = 0; i < kParamSlots; ++i)
-    if (w.slot_done[i]) (void)hipEventDestroy(w.slot_done[i]);
-  if (w.dparams) (void)hipFree(w.dparams);
-  if (w.hslots) (void)hipHostFree(w.hslots);
+  if (w.graph) (void)hipGraphDestroy(w.graph);
   if (w.slot) (void)hipFree(w.slot);
   if (w.state) (void)hipFree(w.state);
   if (w.dmin) (void)hipFree(w.dmin);
@@ -247,6 +240,11 @@ int utf8v_validate_batch_graph(const uint8_t* data, const int64_t* offsets, int6
     if (rc) return rc;
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // a replay recorded into a caller's capture would keep this call's arguments for good
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(st, &cs);
+  if (e != hipSuccess) return hip_fail(e);
+  if (cs != hipStreamCaptureStatusNone) return set_status(UTF8V_EINVAL);
   Workspace* ws = nullptr;
   int rc = workspace(st, &ws);
   if (rc) return rc;
@@ -255,38 +253,25 @@ int utf8v_validate_batch_graph(const uint8_t* data, const int64_t* offsets, int6
   const int cus = num_cus_of(dev) > 0 ? num_cus_of(dev) : 1;
   const utf8v::TuneBatch cfg = tune_batch();
   std::lock_guard<std::mutex> lk(ws->mu);
-  hipError_t e = hipSuccess;
-  if (!ws->dparams) {
-    e = hipMalloc(&ws->dparams, sizeof(utf8v::BatchArgs));
-    if (e == hipSuccess) e = hipHostMalloc(&ws->hslots, sizeof(utf8v::BatchArgs) * kParamSlots, hipHostMallocDefault);
-    for (int i = 0; e == hipSuccess && i < kParamSlots; ++i)
-      e = hipEventCreateWithFlags(&ws->slot_done[i], hipEventDisableTiming);
-    if (e != hipSuccess) return hip_fail(e);
-  }
   if (!ws->exec || ws->graph_waves != cfg.waves_per_cu || ws->graph_cus != cus) {
     if (ws->exec) {
       e = hipStreamSynchronize(st);  // no replay of the old graph may still be running
       if (e != hipSuccess) return hip_fail(e);
       (void)hipGraphExecDestroy(ws->exec);
+      (void)hipGraphDestroy(ws->graph);
       ws->exec = nullptr;
+      ws->graph = nullptr;
     }
-    e = utf8v::capture_batch_graph(ws->dparams, cfg, cus, &ws->exec);
+    e = utf8v::make_batch_graph(cfg, cus, &ws->graph, &ws->exec, &ws->node);
     if (e != hipSuccess) return hip_fail(e);
     ws->graph_waves = cfg.waves_per_cu;
     ws->graph_cus = cus;
   }
-  const int slot = ws->next_slot;
-  ws->next_slot = (slot + 1) % kParamSlots;
-  if (ws->slot_used[slot]) {
-    e = hipEventSynchronize(ws->slot_done[slot]);  // the copy out of this slot has run
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  ws->hslots[slot] = utf8v::batch_args(data, offsets, n, out_flags, out_first_err, ws->slot);
-  e = hipMemcpyAsync(ws->dparams, &ws->hslots[slot], sizeof(utf8v::BatchArgs), hipMemcpyHostToDevice, st);
+  // the new arguments apply to this replay on; replays already enqueued keep theirs
+  e = utf8v::set_batch_graph_args(ws->exec, ws->node,
+                                  utf8v::batch_args(data, offsets, n, out_flags, out_first_err, ws->slot), cfg, cus);
   if (e == hipSuccess) e = hipGraphLaunch(ws->exec, st);
-  if (e == hipSuccess) e = hipEventRecord(ws->slot_done[slot], st);
   if (e != hipSuccess) return hip_fail(e);
-  ws->slot_used[slot] = true;
   return set_status(UTF8V_OK);
 }
 

@@ -57,11 +57,8 @@ struct DevArgs {
   gptr<int64_t> first_err;
 };
 
-// Arguments come by value, or from a device parameter block when pa is not null
-// (graph replays: the captured launches keep pa, only the block's contents change).
 // The buffers are device or pinned host memory, never LDS or scratch.
-__device__ __forceinline__ DevArgs args_of(const BatchArgs& a0, const BatchArgs* pa) {
-  const BatchArgs a = pa ? *pa : a0;
+__device__ __forceinline__ DevArgs args_of(const BatchArgs& a) {
   return DevArgs{(gptr<const uint8_t>)a.data, (gptr<const int64_t>)a.offsets, a.n,
                  (gptr<unsigned long long>)a.slot, (gptr<uint8_t>)a.flags, (gptr<int64_t>)a.first_err};
 }
@@ -299,28 +296,30 @@ __device__ __forceinline__ void write_result(const DevArgs& a, int64_t k, P b, i
 // Wave holding position p (tiles are dealt out in runs of `per`).
 __device__ __forceinline__ int64_t wave_of(int64_t p, int64_t c0, int64_t per) { return (p - c0) / kTile / per; }
 
-// Cross-wave slot word: arrivals in bits 40..63, the least partial first detection in
-// bits 0..39 (kSlotNone = none; a string is shorter than 2^40 bytes).  One 64-bit word,
-// so arrival and minimum are published together without a memory fence.
+// Cross-wave slot word: arrivals in bits 40..63 and, in bits 0..39, the least partial
+// first detection d stored as kSlotMask - d (0 = none; a string is shorter than 2^40 - 1
+// bytes), so an idle slot is all zero and the least detection is the largest stored
+// value.  One 64-bit word, so arrival and minimum are published together without a
+// memory fence.
 constexpr int kSlotShift = 40;
-constexpr uint64_t kSlotNone = (1ull << kSlotShift) - 1;
+constexpr uint64_t kSlotMask = (1ull << kSlotShift) - 1;
 
 // String k runs across waves ws < we; this wave contributes the first detection d it
 // saw in its part (kNoneRel if none).  The last contributor writes the result and
-// empties the slot.  Lane 0.  A contribution that does not lower the slot's
+// returns the slot to zero.  Lane 0.  A contribution that does not lower the slot's
 // detection (the usual case: none) is a plain atomic add of one arrival, so the
 // many waves inside one long string do not contend in compare-and-swap loops.
 __device__ void cross_wave(const DevArgs& a, int64_t k, int64_t st, int64_t en, int64_t d, int64_t c0,
                            int64_t per) {
   const int64_t ws = wave_of(st, c0, per), we = wave_of(en, c0, per);
   const gptr<unsigned long long> slot = a.slot + ws;
-  const uint64_t mine = d == kNoneRel ? kSlotNone : (uint64_t)d;
+  const uint64_t mine = d == kNoneRel ? 0 : kSlotMask - (uint64_t)d;
   uint64_t old = 0;
   bool done = false;
-  if (mine != kSlotNone) {
+  if (mine != 0) {
     old = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while ((old & kSlotNone) > mine) {
-      const uint64_t nw = (old & ~kSlotNone) + (1ull << kSlotShift) + mine;
+    while ((old & kSlotMask) < mine) {
+      const uint64_t nw = (old & ~kSlotMask) + (1ull << kSlotShift) + mine;
       unsigned long long seen = old;
       if (__hip_atomic_compare_exchange_strong(slot, &seen, (unsigned long long)nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT)) {
@@ -332,10 +331,10 @@ __device__ void cross_wave(const DevArgs& a, int64_t k, int64_t st, int64_t en, 
   }
   if (!done) old = __hip_atomic_fetch_add(slot, 1ull << kSlotShift, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if ((int64_t)(old >> kSlotShift) + 1 == we - ws + 1) {
-    const uint64_t prev = old & kSlotNone;
-    const uint64_t best = prev < mine ? prev : mine;
-    __hip_atomic_exchange(slot, (unsigned long long)kSlotNone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    write_result(a, k, a.data + st, en - st, best == kSlotNone ? kNoneRel : (int64_t)best);
+    const uint64_t prev = old & kSlotMask;
+    const uint64_t best = prev > mine ? prev : mine;
+    __hip_atomic_exchange(slot, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    write_result(a, k, a.data + st, en - st, best == 0 ? kNoneRel : (int64_t)(kSlotMask - best));
   }
 }
 
@@ -378,10 +377,8 @@ __device__ __forceinline__ uint32_t bits_to_bytes(uint32_t nib) { return ((nib *
 // Five waves per SIMD: the kernel fits 96 VGPRs (93, no scratch); left to itself the
 // compiler takes 99 and four waves, which costs the resident-grid launches their
 // priority levels.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void batch_main(BatchArgs a0,
-                                                                                        const BatchArgs* pa,
-                                                                                        int level) {
-  const DevArgs a = args_of(a0, pa);
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void batch_main(BatchArgs a0, int level) {
+  const DevArgs a = args_of(a0);
   __shared__ __align__(16) uint8_t sbytes[kTile + kMaskPad];  // tile positions [-16, kTile)
   __shared__ uint32_t sbits[kMaskWords + 1];                   // string starts at positions [-32, kTile)
   __shared__ int64_t soff[kOffCap];                            // offsets[k0 ..] of the window
@@ -702,9 +699,9 @@ hipError_t launch_offsets_check(const int64_t* offsets, int64_t n, int* bad, int
   return hipGetLastError();
 }
 
-// Empty cross-wave slots: no arrivals, no partial detection.
+// Empty cross-wave slots: no arrivals, no partial detection (all zero).
 __global__ void batch_slots_init(unsigned long long* slot, int slots) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < slots; i += gridDim.x * blockDim.x) slot[i] = kSlotNone;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < slots; i += gridDim.x * blockDim.x) slot[i] = 0ull;
 }
 
 hipError_t launch_batch_slots_init(unsigned long long* slot, int slots, hipStream_t st) {
@@ -732,40 +729,64 @@ static int resident_waves_per_cu() {
   return resident;
 }
 
-// One persistent grid of one-wave workgroups (fixed shape, so the same launch
-// serves any batch); pa (device) overrides a when not null.
-static hipError_t launch_batch_kernels(const BatchArgs& a, const BatchArgs* pa, const TuneBatch& cfg, int num_cus,
-                                       hipStream_t st) {
-  const int per_cu = cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1;
-  const int waves = num_cus * per_cu;
-  hipLaunchKernelGGL(batch_main, dim3(waves), dim3(64), 0, st, a, pa, per_cu <= resident_waves_per_cu() ? 1 : 0);
-  return hipGetLastError();
+// One persistent grid of one-wave workgroups: num_cus * waves_per_cu of them, whatever
+// the batch (the kernel reads the byte range from the offsets).
+static int batch_grid(const TuneBatch& cfg, int num_cus) {
+  return num_cus * (cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1);
+}
+
+static int batch_level(const TuneBatch& cfg) {
+  return (cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1) <= resident_waves_per_cu() ? 1 : 0;
 }
 
 hipError_t launch_batch(const BatchArgs& a, const TuneBatch& cfg, int num_cus, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
-  return launch_batch_kernels(a, nullptr, cfg, num_cus, st);
+  hipLaunchKernelGGL(batch_main, dim3(batch_grid(cfg, num_cus)), dim3(64), 0, st, a, batch_level(cfg));
+  return hipGetLastError();
 }
 
 void batch_launch_queries() { (void)resident_waves_per_cu(); }
 
-hipError_t capture_batch_graph(const BatchArgs* dparams, const TuneBatch& cfg, int num_cus, hipGraphExec_t* exec) {
-  batch_launch_queries();  // the occupancy query is not a call to make while capturing
-  hipStream_t cap = nullptr;
-  hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-  if (e != hipSuccess) return e;
-  hipGraph_t graph = nullptr;
-  e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess) {
-    const BatchArgs dummy = batch_args(nullptr, nullptr, 0, nullptr, nullptr, nullptr);
-    hipError_t le = launch_batch_kernels(dummy, dparams, cfg, num_cus, cap);
-    e = hipStreamEndCapture(cap, &graph);
-    if (e == hipSuccess) e = le;
+// Kernel node parameters of one batch launch; args[] must stay alive while they are used.
+static hipKernelNodeParams batch_node_params(void** args, const TuneBatch& cfg, int num_cus) {
+  hipKernelNodeParams p{};
+  p.func = reinterpret_cast<void*>(batch_main);
+  p.gridDim = dim3(batch_grid(cfg, num_cus));
+  p.blockDim = dim3(64);
+  p.sharedMemBytes = 0;
+  p.kernelParams = args;
+  p.extra = nullptr;
+  return p;
+}
+
+// The graph stays alive as long as its executable: the node handle that later argument
+// updates name belongs to it.
+hipError_t make_batch_graph(const TuneBatch& cfg, int num_cus, hipGraph_t* graph, hipGraphExec_t* exec,
+                            hipGraphNode_t* node) {
+  batch_launch_queries();
+  BatchArgs a = batch_args(nullptr, nullptr, 0, nullptr, nullptr, nullptr);
+  int level = batch_level(cfg);
+  void* args[] = {&a, &level};
+  const hipKernelNodeParams p = batch_node_params(args, cfg, num_cus);
+  *graph = nullptr;
+  *exec = nullptr;
+  hipError_t e = hipGraphCreate(graph, 0);
+  if (e == hipSuccess) e = hipGraphAddKernelNode(node, *graph, nullptr, 0, &p);
+  if (e == hipSuccess) e = hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0);
+  if (e != hipSuccess && *graph) {
+    (void)hipGraphDestroy(*graph);
+    *graph = nullptr;
   }
-  if (e == hipSuccess) e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
-  if (graph) (void)hipGraphDestroy(graph);
-  (void)hipStreamDestroy(cap);
   return e;
+}
+
+hipError_t set_batch_graph_args(hipGraphExec_t exec, hipGraphNode_t node, const BatchArgs& a0, const TuneBatch& cfg,
+                                int num_cus) {
+  BatchArgs a = a0;
+  int level = batch_level(cfg);
+  void* args[] = {&a, &level};
+  const hipKernelNodeParams p = batch_node_params(args, cfg, num_cus);
+  return hipGraphExecKernelNodeSetParams(exec, node, &p);
 }
 
 }  // namespace utf8v

@@ -57,7 +57,12 @@ hipError_t launch_batch(const BatchArgs& a, const TuneBatch& cfg, int num_cus, h
 hipError_t launch_batch_slots_init(unsigned long long* slot, int slots, hipStream_t st);
 void batch_launch_queries();   // one-time queries of the batch launch, made outside any stream capture
 void single_launch_queries();  // the same for the single-buffer launches
-hipError_t capture_batch_graph(const BatchArgs* dparams, const TuneBatch& cfg, int num_cus, hipGraphExec_t* exec);
+// A one-node graph of the batch launch (num_cus, cfg fixed), and the update of its
+// arguments before each replay.
+hipError_t make_batch_graph(const TuneBatch& cfg, int num_cus, hipGraph_t* graph, hipGraphExec_t* exec,
+                            hipGraphNode_t* node);
+hipError_t set_batch_graph_args(hipGraphExec_t exec, hipGraphNode_t node, const BatchArgs& a, const TuneBatch& cfg,
+                                int num_cus);
 hipError_t launch_offsets_check(const int64_t* offsets, int64_t n, int* bad, int num_cus, hipStream_t st);
 hipError_t launch_classify(const uint8_t* buf, uint64_t n, uint8_t* sc, uint8_t* err, hipStream_t st);
 hipError_t launch_read_ceiling(const uint8_t* buf, uint64_t n, uint32_t* out, int num_cus, hipStream_t st);

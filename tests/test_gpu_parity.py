@@ -174,19 +174,29 @@ def test_config0_mixed_1mib_and_64_corrupted_copies(u8):
 
 @pytest.mark.parametrize("variant", ["ascii", "latin", "cjk", "emoji", "random"])
 def test_config1_full_size_1gib(u8, variant):
-    """1 GiB buffers at the benchmark's launch configuration, plus the copy with an error in the last 4 bytes."""
-    say(f"case: config1 {variant}")
+    """1 GiB buffers, plus the copy with an error in the last 4 bytes, at the launch shape the
+    benchmark times (unroll 4, 20 waves per CU) with the ASCII skip off and on, and at the
+    library's default configuration."""
     n = 1 << 30
     seed = {"ascii": 1, "latin": 2, "cjk": 3, "emoji": 4, "random": 5}[variant]
     b = synth.text(n, variant, seed)
     t = dev(b)
     exp = oracle.first_error(b)
-    assert u8.first_error(t) == exp
     if variant != "random":
         assert exp == -1
         tail, s, cls = synth.tail_error_copy(b[-64:], seed)
-        t[-64:].copy_(torch.from_numpy(tail))
-        assert u8.first_error(t) == s + n - 64
+        t_err = t.clone()
+        t_err[-64:].copy_(torch.from_numpy(tail))
+    old = u8.get_config()
+    try:
+        for cfg in (dict(unroll=4, waves_per_cu=20, ascii=0), dict(unroll=4, waves_per_cu=20, ascii=1), old):
+            say(f"case: config1 {variant} {cfg}")
+            u8.set_config(**cfg)
+            assert u8.first_error(t) == exp
+            if variant != "random":
+                assert u8.first_error(t_err) == s + n - 64
+    finally:
+        u8.set_config(**old)
     del t
     torch.cuda.empty_cache()
 
@@ -271,6 +281,24 @@ def test_batch_config3_heavy_tail(u8):
     assert np.array_equal(ferr.cpu().numpy(), e_o)
     assert np.array_equal(flags.cpu().numpy(), f_o)
     assert np.array_equal(e_o[expected >= 0], expected[expected >= 0])
+
+
+def test_batch_config3_heavy_tail_4gib(u8):
+    """The heavy tail at x_m 34 KiB: 20,000 Pareto strings, about 4.3 GB, strings up to 64 MiB."""
+    say("case: config3b generate")
+    data, offsets, expected = synth.pareto_batch(20_000, 3, xm=34 * 1024)
+    assert data.size > 4_000_000_000 and int(np.diff(offsets).max()) > 32 << 20
+    f_o, e_o = oracle.first_error_batch(data, offsets)
+    assert np.array_equal(e_o[expected >= 0], expected[expected >= 0])
+    say(f"case: config3b validate {data.size} bytes")
+    td, to = dev(data), dev(offsets)
+    flags, ferr = u8.validate_batch(td, to)
+    torch.cuda.synchronize()
+    assert np.array_equal(ferr.cpu().numpy(), e_o)
+    assert np.array_equal(flags.cpu().numpy(), f_o)
+    assert 50 <= int((f_o == 0).sum()) <= 150
+    del td, to, flags, ferr
+    torch.cuda.empty_cache()
 
 
 def test_batch_strings_across_tiles_and_waves(u8):
@@ -603,6 +631,10 @@ def test_async_calls_captured_in_a_torch_graph(u8):
     with torch.cuda.graph(g, stream=s):
         u8.validate_async(tb, out)
         u8.validate_batch_async(td, to, flags, ferr)
+        # the graph entry point refuses to be recorded (a replay would keep this call's arguments)
+        with pytest.raises(u8.Utf8vError) as ei:
+            u8.validate_batch_graph(td, to, flags, ferr)
+        assert ei.value.status == -1
     for rep in range(4):
         say(f"case: torch graph replay {rep}")
         out.fill_(-9)

@@ -333,3 +333,44 @@ def test_error_class_agrees_with_cpython_reasons():
                     assert cls in cont, (b.hex(), cls)
                 else:
                     assert e.reason == "unexpected end of data" and cls == 2, (b.hex(), cls)
+
+
+def _golden_class_batch():
+    """A CSR batch of the golden rows, with known offsets and classes.
+
+    offsets[0] is not 0 (padding bytes FF, themselves a class-1 error, come first),
+    empty and valid strings sit between the rows, and each truncated row is followed by
+    a string that starts with continuation bytes, so reading past a string's end would
+    complete the truncated character and change its class.
+    """
+    # the golden rows, and characters cut by the string end (section 3 rule b: too short)
+    rows = _golden_classes() + [(b"\xf0\x9f\x98", 0, 2, "cut"), (b"A\xe9\x8f", 1, 2, "cut"), (b"\xc3", 0, 2, "cut")]
+    strs, ferr, cls = [], [], []
+    for i, (b, off, c, _) in enumerate(rows):
+        strs += [b, b"", "é".encode()] if i % 2 else [b]
+        ferr += [off, -1, -1] if i % 2 else [off]
+        cls += [c, 0, 0] if i % 2 else [c]
+        if c == 2:
+            strs.append(b"\x80\xbf\x80\x41")
+            ferr.append(0)
+            cls.append(3)
+    pad = b"\xff" * 7
+    data = np.frombuffer(pad + b"".join(strs), np.uint8)
+    lens = np.array([len(s) for s in strs], np.int64)
+    offsets = len(pad) + np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    return data, offsets, np.array(ferr, np.int64), np.array(cls, np.uint8)
+
+
+def test_error_class_batch_golden():
+    """The batch form slices each string itself: classes of the golden rows at their offsets."""
+    data, offsets, ferr, cls = _golden_class_batch()
+    assert sorted(set(cls.tolist())) == [0, 1, 2, 3, 4, 5, 6]
+    assert offsets[0] != 0 and (np.diff(offsets) == 0).any()
+    got = oracle.error_class_batch(data, offsets, ferr)
+    assert got.tolist() == cls.tolist()
+    # the offsets the classes are computed from are the first-error offsets the oracle reports
+    flags, fe = oracle.first_error_batch(data, offsets)
+    assert fe.tolist() == ferr.tolist() and flags.tolist() == (ferr < 0).astype(np.uint8).tolist()
+    # a batch of nothing but empty strings is all valid
+    e = oracle.error_class_batch(data, np.full(5, 3, np.int64), np.full(4, -1, np.int64))
+    assert e.tolist() == [0, 0, 0, 0]

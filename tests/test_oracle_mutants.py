@@ -156,3 +156,42 @@ def test_unmutated_class_rule_passes(tmp_path):
 def test_class_mutant_is_caught(tmp_path, name):
     old, new = CLASS_MUTANTS[name]
     assert not _class_pins_hold(_build_classes(tmp_path, name, old, new)), f"pins missed mutant: {name}"
+
+
+# ---- the batch form of the error-class rule -----------------------------------------------
+
+CLASS_BATCH_MUTANTS = {
+    "absolute offsets": ("oracle_error_class(data + st, len, first_err[k])",
+                         "oracle_error_class(data, offsets[k + 1], first_err[k])"),
+    "strings run to the batch end": ("int64_t st = offsets[k], len = offsets[k + 1] - st;",
+                                     "int64_t st = offsets[k], len = offsets[n] - st;"),
+    "offset zero taken as valid": ("first_err[k] < 0 ? 0", "first_err[k] <= 0 ? 0"),
+}
+
+
+def _class_batch_pins_hold(lib):
+    import test_oracle as to
+    data, offsets, ferr, cls = to._golden_class_batch()
+    out = np.zeros(cls.size, np.uint8)
+    lib.oracle_error_class_batch(data.ctypes.data, offsets.ctypes.data, cls.size, ferr.ctypes.data,
+                                 out.ctypes.data)
+    return out.tolist() == cls.tolist()
+
+
+def _build_class_batch(tmp_path, name, old, new):
+    lib = _build(tmp_path, name, old, new)
+    lib.oracle_error_class_batch.restype = ctypes.c_int
+    lib.oracle_error_class_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                             ctypes.c_void_p]
+    return lib
+
+
+def test_unmutated_class_batch_passes(tmp_path):
+    marker = "int oracle_error_class_batch("
+    assert _class_batch_pins_hold(_build_class_batch(tmp_path, "same", marker, marker))
+
+
+@pytest.mark.parametrize("name", sorted(CLASS_BATCH_MUTANTS))
+def test_class_batch_mutant_is_caught(tmp_path, name):
+    old, new = CLASS_BATCH_MUTANTS[name]
+    assert not _class_batch_pins_hold(_build_class_batch(tmp_path, name, old, new)), f"pins missed mutant: {name}"
