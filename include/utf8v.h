@@ -105,6 +105,22 @@ int utf8v_validate_batch_graph(const uint8_t *data, const int64_t *offsets, int6
                                uint8_t *out_flags, int64_t *out_first_err, void *stream);
 
 /*
+ * utf8v_validate_batch_noalloc -- as utf8v_validate_batch_async, for callers that
+ * cannot allocate memory (code under stream capture, tight serving loops): it never
+ * calls hipMalloc or any other allocating routine, on any call.  The batch kernel's
+ * cross-wave slots (one 64-bit word per wave of the persistent grid) live in a fixed
+ * device array of 16384 words (128 KiB) that the library holds on every GPU it runs
+ * on until the process ends; a launch configuration whose grid (compute units x
+ * batch_waves_per_cu) needs more words is rejected with UTF8V_EINVAL.  The array is
+ * zero when idle and every finished call leaves it zero.  All calls on one GPU share
+ * it: calls that overlap on one GPU (on different streams, or from different threads
+ * without ordering) race and must not be made.  Inputs, outputs and results are those
+ * of utf8_validate_batch; n == 0 is a no-op.
+ */
+int utf8v_validate_batch_noalloc(const uint8_t *data, const int64_t *offsets, int64_t n,
+                                 uint8_t *out_flags, int64_t *out_first_err, void *stream);
+
+/*
  * utf8v_copy_validate -- enqueue one pass that copies src[0..len) to dst and
  * validates it (first-error offset to *dev_first_err, as utf8v_validate_async):
  * every byte is read once, for both jobs.  src may be device memory or pinned

@@ -49,6 +49,7 @@ SIGNATURES = {
     "utf8_validate_batch": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "utf8v_validate_batch_async": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "utf8v_validate_batch_graph": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
+    "utf8v_validate_batch_noalloc": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "utf8v_check_offsets": (_i32, [_vp, _i64, _vp]),
     "utf8v_get_config": (_i32, [ctypes.POINTER(Config)]),
     "utf8v_set_config": (_i32, [ctypes.POINTER(Config)]),

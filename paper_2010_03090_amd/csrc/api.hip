@@ -10,6 +10,14 @@
 #include "../../include/utf8v.h"
 #include "common.hpp"
 
+// Cross-wave slots of the batch kernel for utf8v_validate_batch_noalloc: one 64-bit word
+// per wave of the persistent grid (CUs x batch waves per CU), all zero when idle.  The
+// loader zero-fills the array and every finished launch leaves it zero again.  Host
+// code never uses this name as an address: each device's copy is reached through the
+// pointer hipGetSymbolAddress gives for it.
+constexpr int kScratchWords = 16384;  // 256 CUs x 64 waves per CU
+static __device__ __align__(256) unsigned long long scratch[kScratchWords];
+
 namespace {
 
 using utf8v::kNone;
@@ -165,9 +173,59 @@ int enqueue_single(const uint8_t* buf, size_t len, int64_t* dev_out, hipStream_t
   return set_status(UTF8V_OK);
 }
 
+// Per device: the address of its copy of `scratch`, and its CU count, found once at the
+// first allocation-free call on the device (with the device current).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch_ptr[kMaxDevices] = {};
+int g_scratch_cus[kMaxDevices] = {};
+
+int scratch_of(int dev, unsigned long long** ptr, int* cus) {
+  if (dev < 0 || dev >= kMaxDevices) return set_status(UTF8V_EINVAL);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    unsigned long long* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e);
+    int v = 0;
+    e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e);
+    utf8v::batch_launch_queries();
+    g_scratch_cus[dev] = v > 0 ? v : 1;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  *cus = g_scratch_cus[dev];
+  return UTF8V_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int utf8v_validate_batch_noalloc(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* out_flags,
+                                 int64_t* out_first_err, void* stream) {
+  if (n < 0) return set_status(UTF8V_EINVAL);
+  if (n == 0) return set_status(UTF8V_OK);
+  if (!data || !offsets || !out_flags || !out_first_err) return set_status(UTF8V_EINVAL);
+  for (const void* p : {(const void*)data, (const void*)offsets, (const void*)out_flags, (const void*)out_first_err}) {
+    int rc = check_device_ptr(p);
+    if (rc) return rc;
+  }
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  unsigned long long* slots = nullptr;
+  int cus = 0;
+  rc = scratch_of(dev, &slots, &cus);
+  if (rc) return rc;
+  const utf8v::TuneBatch cfg = tune_batch();
+  if ((int64_t)cus * (int64_t)cfg.waves_per_cu > kScratchWords) return set_status(UTF8V_EINVAL);
+  hipError_t e = utf8v::launch_batch(utf8v::batch_args(data, offsets, n, out_flags, out_first_err, slots), cfg, cus,
+                                     reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e);
+  return set_status(UTF8V_OK);
+}
 
 int utf8v_validate_ex(const uint8_t* buf, size_t len, int64_t* first_err, void* stream) {
   if ((buf == nullptr && len != 0) || (uint64_t)len >= utf8v::kPosNone) return set_status(UTF8V_EINVAL);

@@ -50,6 +50,9 @@ def test_host_only_error_paths():
     assert lib.utf8v_validate_batch_graph(None, None, -2, None, None, None) == _native.UTF8V_EINVAL
     assert lib.utf8v_validate_batch_graph(None, None, 5, None, None, None) == _native.UTF8V_EINVAL
     assert lib.utf8_validate(None, 3) is False
+    assert lib.utf8v_validate_batch_noalloc(None, None, 0, None, None, None) == 0
+    assert lib.utf8v_validate_batch_noalloc(None, None, -1, None, None, None) == _native.UTF8V_EINVAL
+    assert lib.utf8v_validate_batch_noalloc(None, None, 4, None, None, None) == _native.UTF8V_EINVAL
     # serving: limits are checked before any device call
     cfg = _native.ServerConfig()
     assert lib.utf8v_server_default_config(ctypes.byref(cfg)) == 0
