@@ -330,11 +330,11 @@ def autotune_batch(u8, lib, td, to, n, flags, ferr, rounds=7):
                                  ctypes.byref(best), times, 64)
     if k < 0:
         raise u8.Utf8vError(k, "utf8v_autotune_batch")
-    cands = [f"batch_waves_per_cu={w}" for w in (4, 8, 12, 16, 20, 24, 32, 48, 64)]
+    cands = [f"batch_waves_per_cu={w},batch_ascii={a}" for w in (4, 8, 12, 16, 20, 24, 32, 48, 64) for a in (0, 1)]
     ms = np.array([times[i] for i in range(k)])
     log(f"autotuned batch launch: {best.as_dict()}")
-    return {"chosen": {"batch_waves_per_cu": best.batch_waves_per_cu}, "rounds": rounds,
-            "fastest_ms_x3": _top(cands, ms)}
+    return {"chosen": {"batch_waves_per_cu": best.batch_waves_per_cu, "batch_ascii": best.batch_ascii},
+            "rounds": rounds, "fastest_ms_x3": _top(cands, ms)}
 
 
 def bench_batch(u8, lib, synth, torch, dev, stream, sh, args):
@@ -538,12 +538,14 @@ def bench_copy(u8, synth, torch, dev, stream, args):
         torch.cuda.synchronize()
     row = {"bytes": n}
     t_copy = timed(lambda: u8.copy(src_d, dst), reps)
+    t_rt_copy = timed(lambda: dst.copy_(src_d), reps)   # the runtime's device-to-device copy
     t_val = timed(lambda: u8.validate_async(src_d, out[1:2]), reps)
     t_both = timed(lambda: (u8.copy(src_d, dst), u8.validate_async(src_d, out[1:2])), reps)
     t_fused = timed(lambda: u8.copy_validate(src_d, dst, out[0:1]), reps)
     if int(out[0]) != -1 or not torch.equal(dst[-4096:], src_d[-4096:]):
         raise SystemExit("wrong copy_validate result")
-    row["device_to_device_GBps"] = {"copy": round(n / t_copy / 1e9, 1), "validate": round(n / t_val / 1e9, 1),
+    row["device_to_device_GBps"] = {"copy": round(n / t_copy / 1e9, 1), "runtime_copy": round(n / t_rt_copy / 1e9, 1),
+                                    "validate": round(n / t_val / 1e9, 1),
                                     "copy_then_validate": round(n / t_both / 1e9, 1),
                                     "fused": round(n / t_fused / 1e9, 1)}
     t_h2d = timed(lambda: dst.copy_(src_h, non_blocking=True), 3)

@@ -42,7 +42,7 @@ struct Workspace {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipGraphNode_t node = nullptr;
-  int graph_waves = 0, graph_cus = 0;
+  int graph_waves = 0, graph_cus = 0, graph_ascii = -1;
 };
 
 std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
@@ -311,7 +311,7 @@ int utf8v_validate_batch_graph(const uint8_t* data, const int64_t* offsets, int6
   const int cus = num_cus_of(dev) > 0 ? num_cus_of(dev) : 1;
   const utf8v::TuneBatch cfg = tune_batch();
   std::lock_guard<std::mutex> lk(ws->mu);
-  if (!ws->exec || ws->graph_waves != cfg.waves_per_cu || ws->graph_cus != cus) {
+  if (!ws->exec || ws->graph_waves != cfg.waves_per_cu || ws->graph_cus != cus || ws->graph_ascii != cfg.ascii) {
     if (ws->exec) {
       e = hipStreamSynchronize(st);  // no replay of the old graph may still be running
       if (e != hipSuccess) return hip_fail(e);
@@ -324,6 +324,7 @@ int utf8v_validate_batch_graph(const uint8_t* data, const int64_t* offsets, int6
     if (e != hipSuccess) return hip_fail(e);
     ws->graph_waves = cfg.waves_per_cu;
     ws->graph_cus = cus;
+    ws->graph_ascii = cfg.ascii;
   }
   // the new arguments apply to this replay on; replays already enqueued keep theirs
   e = utf8v::set_batch_graph_args(ws->exec, ws->node,

@@ -63,12 +63,41 @@ __device__ __forceinline__ DevArgs args_of(const BatchArgs& a) {
                  (gptr<unsigned long long>)a.slot, (gptr<uint8_t>)a.flags, (gptr<int64_t>)a.first_err};
 }
 
-// Strings [k0, k1) are valid.
+// Wave-uniform 64-bit value kept in scalar registers.
+__device__ __forceinline__ int64_t uniform(int64_t v) {
+  const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi32 = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi32 << 32) | lo32);
+}
+
+// A wave-uniform address held in scalar registers as it is: per-lane accesses then add a
+// 32-bit lane offset to it (one address register for every base), instead of the
+// compiler keeping 64-bit per-lane addresses live across the loop.
+template <class T>
+__device__ __forceinline__ gptr<T> sgpr_base(gptr<T> p) {
+  uint64_t v = (uint64_t)p;
+  asm volatile("" : "+s"(v));
+  return (gptr<T>)v;
+}
+
+// Strings [k0, k1) are valid.  Each pass stores 64 results at a wave-uniform base.
 __device__ __forceinline__ void write_valid(const DevArgs& a, int64_t k0, int64_t k1, int lane) {
-  for (int64_t k = k0 + lane; k < k1; k += 64) {
-    a.flags[k] = 1;
-    a.first_err[k] = -1;
+  k0 = uniform(k0);
+  k1 = uniform(k1);
+  for (int64_t k = k0; k < k1; k += 64) {
+    if (lane < k1 - k) {
+      sgpr_base(a.flags + k)[lane] = 1;
+      sgpr_base(a.first_err + k)[lane] = -1;
+    }
   }
+}
+
+// Position of boundary v relative to the tile start ts, for v >= ts - 8; positions past
+// the tile only have to compare as such, so they saturate at kRelFar.
+constexpr int32_t kRelFar = 1 << 30;
+__device__ __forceinline__ int32_t tile_rel(int64_t v, int64_t ts) {
+  const int64_t d = v - ts;
+  return d < (int64_t)kRelFar ? (int32_t)d : kRelFar;
 }
 
 // Workgroups are dealt to the XCDs in turn (workgroup b runs on XCD b % kXcds), and
@@ -80,12 +109,6 @@ __device__ __forceinline__ int64_t logical_wave(int64_t b, int64_t g) {
   return g % kXcds ? b : (b % kXcds) * (g / kXcds) + b / kXcds;
 }
 
-// Wave-uniform 64-bit value kept in scalar registers.
-__device__ __forceinline__ int64_t uniform(int64_t v) {
-  const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi32 = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
-  return (int64_t)(((uint64_t)hi32 << 32) | lo32);
-}
 
 // 64-bit value of lane `src` (0..63) of the wave.
 __device__ __forceinline__ int64_t lane_value(int64_t x, int src) {
@@ -194,9 +217,9 @@ __device__ __forceinline__ bool edge_tile(int64_t ts, int64_t lo, int64_t hi) {
 __device__ __forceinline__ void batch_load(u32x4 (&x)[kU], gptr<const uint8_t> data, int64_t ts, int64_t lo,
                                            int64_t hi, int lane) {
   if (!edge_tile(ts, lo, hi)) {
+    const gptr<const u32x4> tile = sgpr_base(reinterpret_cast<gptr<const u32x4>>(data + ts));
 #pragma unroll
-    for (int u = 0; u < kU; ++u)
-      x[u] = __builtin_nontemporal_load(reinterpret_cast<gptr<const u32x4>>(data + ts + u * 1024 + lane * 16));
+    for (int u = 0; u < kU; ++u) x[u] = __builtin_nontemporal_load(tile + u * 64 + lane);
   } else {
 #pragma unroll
     for (int u = 0; u < kU; ++u) x[u] = edge_load(data, ts + u * 1024 + lane * 16, lo, hi);
@@ -377,6 +400,7 @@ __device__ __forceinline__ uint32_t bits_to_bytes(uint32_t nib) { return ((nib *
 // Five waves per SIMD: the kernel fits 96 VGPRs (93, no scratch); left to itself the
 // compiler takes 99 and four waves, which costs the resident-grid launches their
 // priority levels.
+template <bool ASCII>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void batch_main(BatchArgs a0, int level) {
   const DevArgs a = args_of(a0);
   __shared__ __align__(16) uint8_t sbytes[kTile + kMaskPad];  // tile positions [-16, kTile)
@@ -391,13 +415,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
   const int64_t n = a.n;
   const int64_t lo = uniform(offsets[0]), hi = uniform(offsets[n]);
   const int64_t c0 = lo - (int64_t)((reinterpret_cast<uintptr_t>(data) + (uintptr_t)lo) & 15);
-  // tiles cover [c0, hi]: position hi holds the end check of the last string
-  const int64_t tiles = (hi + 1 - c0 + kTile - 1) / kTile;
-  const int64_t per = (tiles + gridDim.x - 1) / gridDim.x;
-  int64_t t = logical_wave(blockIdx.x, gridDim.x) * per;
-  const int64_t t_end = t + per < tiles ? t + per : tiles;
-  if (t >= t_end) return;
-  const int64_t wave_lo = c0 + t * kTile;
+  // tiles cover [c0, hi]: position hi holds the end check of the last string.  Tile
+  // indices are 32-bit (a batch range below 8 TiB), so the loop's comparisons stay scalar.
+  const int64_t tiles64 = (hi + 1 - c0 + kTile - 1) / kTile;
+  const int64_t per = (tiles64 + gridDim.x - 1) / gridDim.x;
+  const int64_t t64 = logical_wave(blockIdx.x, gridDim.x) * per;
+  if (t64 >= tiles64) return;
+  int t = (int)t64;
+  const int t_end = (int)(t64 + per < tiles64 ? t64 + per : tiles64);
+  const int64_t wave_lo = c0 + (int64_t)t * kTile;
   regm[lane] = regm[lane + 64] = 0u;
   endm[lane] = endm[lane + 64] = 0u;
   // the first tile's bytes do not depend on the boundary search: requested before it
@@ -420,36 +446,39 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
   // strings found valid in the previous tile, written during the next one (see step 2)
   int64_t pend_lo = 0, pend_hi = 0;
 
-  PriorityLevels levels(level != 0, t, t_end - t);
+  PriorityLevelsT<int> levels(level != 0, t, t_end - t);
   for (; t < t_end; ++t) {
     levels.step(t);
-    const int64_t ts = c0 + t * kTile;
+    const int64_t ts = c0 + (int64_t)t * kTile;
     const int64_t te = ts + kTile;
-    // 1. boundaries of the window [ts-4, te): [k0, k1), those in [ts, te): [kb, k1).  A tile
-    // inside one string (the window's first boundary lies past it) has none.
-    const bool plain = uniform(v) >= te;
-    int64_t cnt = 0, cnt_next = 0, cnt_before = 0;
-    if (!plain) {
-      for (;;) {
-        const bool in = v < te;
-        if (in && cnt + lane < kOffCap) soff[cnt + lane] = v;
-        const int c = __popcll(__ballot(in));
-        cnt_next += __popcll(__ballot(v < te - 4));
-        cnt_before += __popcll(__ballot(v < ts));
+    // 1. boundaries of the window [ts-4, te): [k0, k1), those in [ts, te): [kb, k1).  Lane l
+    // holds boundary k0 + l, as a 32-bit position relative to ts.  A tile inside one string
+    // (the window's first boundary lies past it) has none; a tile with 64 or more is dense:
+    // its boundaries are counted window by window, the first kOffCap kept in LDS.
+    const int32_t rv = tile_rel(v, ts);
+    int cnt = __popcll(__ballot(rv < kTile));
+    int cnt_next = __popcll(__ballot(rv < kTile - 4));
+    int cnt_before = __popcll(__ballot(rv < 0));
+    const bool plain = cnt == 0;
+    const bool dense = cnt == 64;
+    if (dense) {
+      soff[lane] = v;
+      for (int64_t kk = k0 + 64;; kk += 64) {
+        const int64_t idx = kk + lane;
+        const int64_t w = idx <= n ? offsets[idx] : INT64_MAX;
+        if (kk - k0 + lane < kOffCap) soff[kk - k0 + lane] = w;
+        const int32_t rw = tile_rel(w, ts);
+        const int c = __popcll(__ballot(rw < kTile));
         cnt += c;
+        cnt_next += __popcll(__ballot(rw < kTile - 4));
+        cnt_before += __popcll(__ballot(rw < 0));
         if (c < 64) break;
-        const int64_t idx = k0 + cnt + lane;
-        v = idx <= n ? offsets[idx] : INT64_MAX;
       }
     }
-    const int64_t k1 = uniform(k0 + cnt);
-    const int64_t kb = uniform(k0 + cnt_before);
+    const int64_t k1 = k0 + cnt;
+    const int64_t kb = k0 + cnt_before;
     // a window of at most 63 boundaries is held whole by the lanes: lane l has boundary k0 + l
     const int64_t vwin = v;
-    // Nothing but the scan's own loads is outstanding here.  Waiting for them now (vmcnt(0);
-    // expcnt and lgkmcnt left alone) keeps the compiler from waiting for v after the stores
-    // below, where, the store count being dynamic, it could only wait for those stores too.
-    __builtin_amdgcn_s_waitcnt(0x0F70);
     // 2. the previous tile's valid strings are written here, before tile t+1 is requested: a
     // load's wait also waits for every store issued before it, so these stores get a tile's
     // time to complete.  Then request tile t+1 (its window starts at boundary k0 + cnt_next).
@@ -459,12 +488,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
     if (t + 1 < t_end) {
       batch_load(nx, data, te, lo, hi, lane);
       batch_mask(nx, te, lo, hi, lane);
-      if (!plain) v = k0n + lane <= n ? offsets[k0n + lane] : INT64_MAX;  // (plain: the same window)
+      if (!plain) {  // (plain: the same window)
+        if (k0n + 63 <= n) v = sgpr_base(offsets + k0n)[lane];
+        else v = k0n + lane <= n ? offsets[k0n + lane] : INT64_MAX;
+      }
     }
     __syncthreads();
-    if (open_k == -2) {  // first tile of the wave
+    if (open_k == -2) {  // first tile of the wave: the string open at its start began before it
       open_k = kb - 1;
-      if (open_k >= 0) open_st = uniform(boundary(open_k, offsets, k0, k1, soff));
+      if (open_k >= 0) open_st = uniform(offsets[open_k]);
     }
     // 3. the dword before each chunk: lane l-1's last dword (lane 0: lane 63 of the previous slab)
     uint32_t prev[kU];
@@ -478,7 +510,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
     carry2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)x[kU - 1].z, kDppWaveRor1, 0xF, 0xF, true);
     // 4. plain checks; a tile that is all ASCII with an ASCII halo cannot hold an error (6.4)
     bool run = true;
-    if (ascii.due()) {
+    if (ASCII && ascii.due()) {
       uint32_t o = 0;
 #pragma unroll
       for (int u = 0; u < kU; ++u) o |= x[u].x | x[u].y | x[u].z | x[u].w | prev[u];
@@ -517,8 +549,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
       // 6. the end check (6.3) on the plain bytes before every string boundary in [ts-2, te).
       // A failed check at b leaves the plain checks at b, b+1 and b+2 unreliable: their slabs
       // are rechecked.
-      if (cnt < 64) {
-        if (lane < cnt) m |= end_check_slabs(tile_bytes, (int)(vwin - ts)) << 4;
+      if (!dense) {
+        if (lane < cnt) m |= end_check_slabs(tile_bytes, tile_rel(vwin, ts)) << 4;
       } else {
         for (int64_t k = k0 + lane; k - lane < k1; k += 64)
           if (k < k1) m |= end_check_slabs(tile_bytes, (int)(boundary(k, offsets, k0, k1, soff) - ts)) << 4;
@@ -721,12 +753,18 @@ BatchArgs batch_args(const uint8_t* data, const int64_t* offsets, int64_t n, uin
 // One-wave workgroups of batch_main that a CU holds at once (its registers decide);
 // asked once per process, when a stream's workspace is made and before the graph
 // form's capture, so never while a stream is being captured.
-static int resident_waves_per_cu() {
+template <bool ASCII>
+static int resident_waves_per_cu_t() {
   static const int resident = [] {
     int blocks = 0;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_main, 64, 0) == hipSuccess ? blocks : 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_main<ASCII>, 64, 0) == hipSuccess ? blocks
+                                                                                                       : 0;
   }();
   return resident;
+}
+
+static int resident_waves_per_cu(bool ascii) {
+  return ascii ? resident_waves_per_cu_t<true>() : resident_waves_per_cu_t<false>();
 }
 
 // One persistent grid of one-wave workgroups: num_cus * waves_per_cu of them, whatever
@@ -736,21 +774,27 @@ static int batch_grid(const TuneBatch& cfg, int num_cus) {
 }
 
 static int batch_level(const TuneBatch& cfg) {
-  return (cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1) <= resident_waves_per_cu() ? 1 : 0;
+  return (cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1) <= resident_waves_per_cu(cfg.ascii != 0) ? 1 : 0;
 }
 
 hipError_t launch_batch(const BatchArgs& a, const TuneBatch& cfg, int num_cus, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(batch_main, dim3(batch_grid(cfg, num_cus)), dim3(64), 0, st, a, batch_level(cfg));
+  if (cfg.ascii)
+    hipLaunchKernelGGL(batch_main<true>, dim3(batch_grid(cfg, num_cus)), dim3(64), 0, st, a, batch_level(cfg));
+  else
+    hipLaunchKernelGGL(batch_main<false>, dim3(batch_grid(cfg, num_cus)), dim3(64), 0, st, a, batch_level(cfg));
   return hipGetLastError();
 }
 
-void batch_launch_queries() { (void)resident_waves_per_cu(); }
+void batch_launch_queries() {
+  (void)resident_waves_per_cu(true);
+  (void)resident_waves_per_cu(false);
+}
 
 // Kernel node parameters of one batch launch; args[] must stay alive while they are used.
 static hipKernelNodeParams batch_node_params(void** args, const TuneBatch& cfg, int num_cus) {
   hipKernelNodeParams p{};
-  p.func = reinterpret_cast<void*>(batch_main);
+  p.func = cfg.ascii ? reinterpret_cast<void*>(batch_main<true>) : reinterpret_cast<void*>(batch_main<false>);
   p.gridDim = dim3(batch_grid(cfg, num_cus));
   p.blockDim = dim3(64);
   p.sharedMemBytes = 0;

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <limits>
+
 namespace utf8v {
 
 constexpr uint64_t kNone = ~uint64_t(0);          // "no error detected" for 64-bit positions
@@ -18,7 +20,7 @@ struct TuneSingle {
 
 struct TuneBatch {
   int waves_per_cu = 16;      // persistent grid: one-wave workgroups per compute unit
-  int ascii = 1;
+  int ascii = 1;              // section 6.4 test of all-ASCII tiles (with its back-off)
 };
 
 // State word of a single-buffer call: arrivals << kStateShift | least detection
@@ -90,23 +92,26 @@ __device__ __forceinline__ void set_priority(int p) {
 }
 
 // The priority levels of a run of `count` tiles from tile `first`: level 3 - k from the
-// tile ceil(k * count / 4) tiles into the run.  Wave-uniform; step() at each tile.
-struct PriorityLevels {
-  int64_t first, count, next;
+// tile ceil(k * count / 4) tiles into the run.  Wave-uniform; step() at each tile.  I is
+// the tile index type (a 32-bit index keeps the comparisons scalar).
+template <class I>
+struct PriorityLevelsT {
+  I first, count, next;
   int prio = 3;
   bool on;
-  __device__ PriorityLevels(bool level, int64_t first_tile, int64_t tiles)
+  __device__ PriorityLevelsT(bool level, I first_tile, I tiles)
       : first(first_tile), count(tiles), next(first_tile + (tiles + 3) / 4), on(level) {
     if (on) set_priority(3);
   }
-  __device__ __forceinline__ void step(int64_t t) {
+  __device__ __forceinline__ void step(I t) {
     if (!on || t < next) return;
     do {
       --prio;
-      next = prio > 0 ? first + ((4 - prio) * count + 3) / 4 : INT64_MAX;
+      next = prio > 0 ? first + ((4 - prio) * count + 3) / 4 : std::numeric_limits<I>::max();
     } while (t >= next);
     set_priority(prio);
   }
 };
+using PriorityLevels = PriorityLevelsT<int64_t>;
 
 }  // namespace utf8v

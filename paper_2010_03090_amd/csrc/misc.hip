@@ -67,9 +67,23 @@ __global__ __launch_bounds__(256) void read_or(const uint8_t* __restrict__ buf, 
   }
 }
 
-__global__ __launch_bounds__(256) void copy16(const uint4* __restrict__ s, uint4* __restrict__ d, uint64_t words) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) d[i] = s[i];
+// Copy ceiling: each wave moves one 4 KiB tile (four 16-byte loads per lane in flight,
+// then four stores; both non-temporal), the last block also the tail past whole tiles.
+__global__ __launch_bounds__(256) void copy_tiles(const uint8_t* __restrict__ s, uint8_t* __restrict__ d, uint64_t n) {
+  const uint64_t tiles = n / 4096;
+  const uint64_t wave = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint64_t lane = threadIdx.x & 63;
+  if (wave < tiles) {
+    const uint64_t base = wave * 4096 + lane * 16;
+    u32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(s + base + u * 1024));
+#pragma unroll
+    for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(v[u], reinterpret_cast<u32x4*>(d + base + u * 1024));
+  }
+  if (blockIdx.x == gridDim.x - 1)
+    for (uint64_t i = tiles * 4096 + (uint64_t)threadIdx.x * 16; i < n; i += 256 * 16)
+      *reinterpret_cast<u32x4*>(d + i) = *reinterpret_cast<const u32x4*>(s + i);
 }
 
 hipError_t launch_read_ceiling(const uint8_t* buf, uint64_t n, uint32_t* out, int num_cus, hipStream_t st) {
@@ -81,8 +95,10 @@ hipError_t launch_read_ceiling(const uint8_t* buf, uint64_t n, uint32_t* out, in
 }
 
 hipError_t launch_copy(const uint8_t* src, uint8_t* dst, uint64_t n, int num_cus, hipStream_t st) {
-  hipLaunchKernelGGL(copy16, dim3((unsigned)(num_cus * 8)), dim3(256), 0, st,
-                     reinterpret_cast<const uint4*>(src), reinterpret_cast<uint4*>(dst), n / 16);
+  (void)num_cus;
+  const uint64_t waves = n / 4096;
+  const unsigned blocks = (unsigned)((waves + 3) / 4 > 0 ? (waves + 3) / 4 : 1);
+  hipLaunchKernelGGL(copy_tiles, dim3(blocks), dim3(256), 0, st, src, dst, n);
   return hipGetLastError();
 }
 

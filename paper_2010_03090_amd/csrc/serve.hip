@@ -325,6 +325,7 @@ bool utf8v_server::launch_batch_of(uint64_t first, uint64_t count) {
     utf8v_config c;
     utf8v_get_config(&c);
     tb.waves_per_cu = c.batch_waves_per_cu;
+    tb.ascii = c.batch_ascii;
     const Slot& s0 = slot(first);
     e = utf8v::launch_batch(batch_args(data, offs, plan.strings, direct ? s0.flags : flags,
                                        direct ? s0.errs : errs, wslots),
@@ -622,6 +623,7 @@ int utf8v_serve_replay(const utf8v_server_config* cfg, int mode, const uint8_t* 
   utf8v_get_config(&c);
   TuneBatch tb;
   tb.waves_per_cu = c.batch_waves_per_cu;
+  tb.ascii = c.batch_ascii;
   const int64_t t0 = now_ns() + 2000000;
   for (int64_t i = 0; i < nreq && e == hipSuccess; ++i) {
     wait_until(t0 + arrival_ns[i]);

@@ -602,6 +602,18 @@ def test_copy_validate(u8):
                 assert (d[:off + 16] == 0xAB).all() and (d[off + 16 + n:] == 0xAB).all()   # nothing outside dst
 
 
+def test_copy_kernel(u8):
+    """The copy kernel used as the copy ceiling moves every byte (whole tiles and the tail)."""
+    rng = np.random.default_rng(81)
+    for n in (16, 4096, 3 * 4096 + 16, 1 << 20, (5 << 20) + 4096 + 48):
+        say(f"case: copy {n}")
+        src = dev(np.frombuffer(rng.bytes(n), np.uint8))
+        dst = torch.full((n + 64,), 0xAB, dtype=torch.uint8, device="cuda")
+        u8.copy(src, dst)
+        torch.cuda.synchronize()
+        assert torch.equal(dst[:n], src) and bool((dst[n:] == 0xAB).all())
+
+
 def test_copy_validate_rejects_misaligned_or_overlapping(u8):
     lib = u8.load()
     t = torch.zeros(4096, dtype=torch.uint8, device="cuda")
