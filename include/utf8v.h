@@ -80,7 +80,8 @@ int utf8v_validate_async(const uint8_t *buf, size_t len, int64_t *dev_first_err,
  * check (section 6.3).  Outputs (device memory, n entries each):
  *   out_flags[k]     = 1 if string k is valid UTF-8, else 0;
  *   out_first_err[k] = first-error offset RELATIVE to the string start, or -1.
- * n == 0 is a no-op.  Synchronous on the default stream.  Offsets are trusted:
+ * n == 0 is a no-op; n must be below 2^31 - 64 (else UTF8V_EINVAL: the kernel counts
+ * string indices in 32 bits).  Synchronous on the default stream.  Offsets are trusted:
  * decreasing or out-of-range offsets give undefined results (use
  * utf8v_check_offsets first when they come from untrusted input).
  */

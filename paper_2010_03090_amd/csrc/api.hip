@@ -205,7 +205,7 @@ extern "C" {
 
 int utf8v_validate_batch_noalloc(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* out_flags,
                                  int64_t* out_first_err, void* stream) {
-  if (n < 0) return set_status(UTF8V_EINVAL);
+  if (n < 0 || n > utf8v::kMaxBatchStrings) return set_status(UTF8V_EINVAL);
   if (n == 0) return set_status(UTF8V_OK);
   if (!data || !offsets || !out_flags || !out_first_err) return set_status(UTF8V_EINVAL);
   for (const void* p : {(const void*)data, (const void*)offsets, (const void*)out_flags, (const void*)out_first_err}) {
@@ -259,7 +259,7 @@ int utf8v_validate_async(const uint8_t* buf, size_t len, int64_t* dev_first_err,
 
 int utf8v_validate_batch_async(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* out_flags,
                                int64_t* out_first_err, void* stream) {
-  if (n < 0) return set_status(UTF8V_EINVAL);
+  if (n < 0 || n > utf8v::kMaxBatchStrings) return set_status(UTF8V_EINVAL);
   if (n == 0) return set_status(UTF8V_OK);
   if (!data || !offsets || !out_flags || !out_first_err) return set_status(UTF8V_EINVAL);
   for (const void* p : {(const void*)data, (const void*)offsets, (const void*)out_flags, (const void*)out_first_err}) {
@@ -290,7 +290,7 @@ int utf8_validate_batch(const uint8_t* data, const int64_t* offsets, int64_t n, 
 
 int utf8v_validate_batch_graph(const uint8_t* data, const int64_t* offsets, int64_t n, uint8_t* out_flags,
                                int64_t* out_first_err, void* stream) {
-  if (n < 0) return set_status(UTF8V_EINVAL);
+  if (n < 0 || n > utf8v::kMaxBatchStrings) return set_status(UTF8V_EINVAL);
   if (n == 0) return set_status(UTF8V_OK);
   if (!data || !offsets || !out_flags || !out_first_err) return set_status(UTF8V_EINVAL);
   for (const void* p : {(const void*)data, (const void*)offsets, (const void*)out_flags, (const void*)out_first_err}) {

@@ -81,10 +81,10 @@ __device__ __forceinline__ gptr<T> sgpr_base(gptr<T> p) {
 }
 
 // Strings [k0, k1) are valid.  Each pass stores 64 results at a wave-uniform base.
-__device__ __forceinline__ void write_valid(const DevArgs& a, int64_t k0, int64_t k1, int lane) {
-  k0 = uniform(k0);
-  k1 = uniform(k1);
-  for (int64_t k = k0; k < k1; k += 64) {
+__device__ __forceinline__ void write_valid(const DevArgs& a, int k0, int k1, int lane) {
+  k0 = __builtin_amdgcn_readfirstlane(k0);
+  k1 = __builtin_amdgcn_readfirstlane(k1);
+  for (int k = k0; k < k1; k += 64) {
     if (lane < k1 - k) {
       sgpr_base(a.flags + k)[lane] = 1;
       sgpr_base(a.first_err + k)[lane] = -1;
@@ -207,16 +207,13 @@ __device__ __forceinline__ int64_t window_uniform(int64_t vwin, int64_t k, int64
 }
 
 // Loads of one tile: interior tiles read whole chunks (non-temporal); tiles at the
-// edges of the batch range read the chunks that hold batch bytes, and batch_mask
-// clears the bytes outside the range (right away, or for a wave's first tile after
-// the boundary search, so the loads stay in flight during it).
-__device__ __forceinline__ bool edge_tile(int64_t ts, int64_t lo, int64_t hi) {
-  return !(ts - 4 >= lo && ts + kTile <= hi);
-}
-
+// edges of the batch range (edge: the tile or the 4 bytes before it reach outside
+// [lo, hi)) read the chunks that hold batch bytes, and batch_mask clears the bytes
+// outside the range (right away, or for a wave's first tile after the boundary search,
+// so the loads stay in flight during it).
 __device__ __forceinline__ void batch_load(u32x4 (&x)[kU], gptr<const uint8_t> data, int64_t ts, int64_t lo,
-                                           int64_t hi, int lane) {
-  if (!edge_tile(ts, lo, hi)) {
+                                           int64_t hi, int lane, bool edge) {
+  if (!edge) {
     const gptr<const u32x4> tile = sgpr_base(reinterpret_cast<gptr<const u32x4>>(data + ts));
 #pragma unroll
     for (int u = 0; u < kU; ++u) x[u] = __builtin_nontemporal_load(tile + u * 64 + lane);
@@ -226,8 +223,8 @@ __device__ __forceinline__ void batch_load(u32x4 (&x)[kU], gptr<const uint8_t> d
   }
 }
 
-__device__ __forceinline__ void batch_mask(u32x4 (&x)[kU], int64_t ts, int64_t lo, int64_t hi, int lane) {
-  if (edge_tile(ts, lo, hi)) {
+__device__ __forceinline__ void batch_mask(u32x4 (&x)[kU], int64_t ts, int64_t lo, int64_t hi, int lane, bool edge) {
+  if (edge) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) x[u] = edge_mask(x[u], ts + u * 1024 + lane * 16, lo, hi);
   }
@@ -426,13 +423,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
   const int64_t wave_lo = c0 + (int64_t)t * kTile;
   regm[lane] = regm[lane + 64] = 0u;
   endm[lane] = endm[lane + 64] = 0u;
+  // Tiles whose chunks and the 4 bytes before them lie inside the batch range [lo, hi)
+  // read whole chunks; the others (the first and last tiles of the range) are masked.
+  const int64_t in_first64 = (lo + 4 - c0 + kTile - 1) / kTile;
+  const int64_t in_last64 = hi - kTile - c0 >= 0 ? (hi - kTile - c0) / kTile : -1;
+  const int t_in_first = (int)(in_first64 < tiles64 ? in_first64 : tiles64);
+  const int t_in_last = (int)in_last64;
   // the first tile's bytes do not depend on the boundary search: requested before it
   u32x4 x[kU];
-  batch_load(x, data, wave_lo, lo, hi, lane);
+  const bool edge0 = t < t_in_first || t > t_in_last;
+  batch_load(x, data, wave_lo, lo, hi, lane, edge0);
   const u32x4 before = edge_load(data, wave_lo - 16, lo, hi);  // the 16 bytes before the first tile
+  // String indices are 32-bit: a batch holds fewer than 2^31 - 64 strings (the host checks).
+  const int n32 = (int)n;
   int64_t v;
-  int64_t k0 = uniform(wave_window(offsets, n, lo, hi, wave_lo - 4, lane, v));
-  batch_mask(x, wave_lo, lo, hi, lane);
+  int k0 = (int)uniform(wave_window(offsets, n, lo, hi, wave_lo - 4, lane, v));
+  batch_mask(x, wave_lo, lo, hi, lane, edge0);
   const u32x4 bm = wave_lo - 16 >= lo && wave_lo <= hi ? before : edge_mask(before, wave_lo - 16, lo, hi);
   uint32_t carry = bm.w;    // the dword before the first tile
   uint32_t carry2 = bm.z;   // and the one before that
@@ -441,10 +447,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
   // the short form for 1- and 2-byte text, first tested on the wave's fourth tile: a wave
   // of a batch of short mixed strings has few tiles and would pay for a test in half of them
   AsciiBackoff two{3, 7};
-  // the string open at the wave start (it began in an earlier wave) is found in the first window
-  int64_t open_k = -2, open_st = 0, open_d = kNoneRel;
+  // The string open at the tile start: index, start position and first detection so far.
+  // The one open at the wave start began before the wave (open_first): its result goes
+  // through the cross-wave slot.
+  int open_k = -2;
+  bool open_first = true;
+  int64_t open_st = 0, open_d = kNoneRel;
   // strings found valid in the previous tile, written during the next one (see step 2)
-  int64_t pend_lo = 0, pend_hi = 0;
+  int pend_lo = 0, pend_hi = 0;
 
   PriorityLevelsT<int> levels(level != 0, t, t_end - t);
   for (; t < t_end; ++t) {
@@ -463,9 +473,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
     const bool dense = cnt == 64;
     if (dense) {
       soff[lane] = v;
-      for (int64_t kk = k0 + 64;; kk += 64) {
-        const int64_t idx = kk + lane;
-        const int64_t w = idx <= n ? offsets[idx] : INT64_MAX;
+      for (int kk = k0 + 64;; kk += 64) {
+        const int idx = kk + lane;
+        const int64_t w = idx <= n32 ? offsets[idx] : INT64_MAX;
         if (kk - k0 + lane < kOffCap) soff[kk - k0 + lane] = w;
         const int32_t rw = tile_rel(w, ts);
         const int c = __popcll(__ballot(rw < kTile));
@@ -475,8 +485,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
         if (c < 64) break;
       }
     }
-    const int64_t k1 = k0 + cnt;
-    const int64_t kb = k0 + cnt_before;
+    const int k1 = k0 + cnt;
+    const int kb = k0 + cnt_before;
     // a window of at most 63 boundaries is held whole by the lanes: lane l has boundary k0 + l
     const int64_t vwin = v;
     // 2. the previous tile's valid strings are written here, before tile t+1 is requested: a
@@ -484,13 +494,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
     // time to complete.  Then request tile t+1 (its window starts at boundary k0 + cnt_next).
     write_valid(a, pend_lo, pend_hi, lane);
     u32x4 nx[kU];
-    const int64_t k0n = k0 + cnt_next;
+    const int k0n = k0 + cnt_next;
     if (t + 1 < t_end) {
-      batch_load(nx, data, te, lo, hi, lane);
-      batch_mask(nx, te, lo, hi, lane);
+      const bool edge1 = t + 1 < t_in_first || t + 1 > t_in_last;
+      batch_load(nx, data, te, lo, hi, lane, edge1);
+      batch_mask(nx, te, lo, hi, lane, edge1);
       if (!plain) {  // (plain: the same window)
-        if (k0n + 63 <= n) v = sgpr_base(offsets + k0n)[lane];
-        else v = k0n + lane <= n ? offsets[k0n + lane] : INT64_MAX;
+        if (k0n + 63 <= n32) v = sgpr_base(offsets + k0n)[lane];
+        else v = k0n + lane <= n32 ? offsets[k0n + lane] : INT64_MAX;
       }
     }
     __syncthreads();
@@ -552,7 +563,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
       if (!dense) {
         if (lane < cnt) m |= end_check_slabs(tile_bytes, tile_rel(vwin, ts)) << 4;
       } else {
-        for (int64_t k = k0 + lane; k - lane < k1; k += 64)
+        for (int k = k0 + lane; k - lane < k1; k += 64)
           if (k < k1) m |= end_check_slabs(tile_bytes, (int)(boundary(k, offsets, k0, k1, soff) - ts)) << 4;
       }
     }
@@ -579,13 +590,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
         sbits[lane + 64] = 0u;
         if (lane0) sbits[kMaskWords] = 0u;
         __syncthreads();
-        if (cnt < 64) {
+        if (!dense) {
           if (lane < cnt) {
             const int r = (int)(vwin - ts) + 32;  // bit index, >= 28
             atomicOr(&sbits[r >> 5], 1u << (r & 31));
           }
         } else {
-          for (int64_t k = k0 + lane; k - lane < k1; k += 64) {
+          for (int k = k0 + lane; k - lane < k1; k += 64) {
             if (k < k1) {
               const int64_t r = boundary(k, offsets, k0, k1, soff) - ts + 32;  // bit index, >= 28
               atomicOr(&sbits[r >> 5], 1u << (r & 31));
@@ -645,36 +656,40 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
     pend_lo = pend_hi = kb;
     if (open_k >= 0) {  // the string open at ts
       const bool ends = kb < k1;
-      const int64_t en = !ends ? te
-                         : cnt < 64 ? window_uniform(vwin, kb, k0)
+      if (tile_bad || (ends && (open_first || open_d != kNoneRel))) {
+        const int64_t en = !ends ? te
+                           : !dense ? window_uniform(vwin, kb, k0)
                                     : uniform(boundary(kb, offsets, k0, k1, soff));
-      if (tile_bad) {
-        const int r = first_bit(regm, nz, 0, (int)(en - ts));
-        if (r >= 0 && ts + r - open_st < open_d) open_d = ts + r - open_st;
-        if (ends && bit_at(endm, (int)(en - ts)) && en - open_st < open_d) open_d = en - open_st;
-      }
-      if (ends) {
-        if (open_st < wave_lo) {
-          if (lane0) cross_wave(a, open_k, open_st, en, open_d, c0, per);
-        } else if (open_d == kNoneRel) {
-          pend_lo = open_k;  // = kb - 1, written with the tile's valid strings
-        } else if (lane0) {
-          write_result(a, open_k, data + open_st, en - open_st, open_d);
+        if (tile_bad) {
+          const int r = first_bit(regm, nz, 0, (int)(en - ts));
+          if (r >= 0 && ts + r - open_st < open_d) open_d = ts + r - open_st;
+          if (ends && bit_at(endm, (int)(en - ts)) && en - open_st < open_d) open_d = en - open_st;
         }
-        open_k = -1;
+        if (ends) {
+          if (open_first) {  // it began in an earlier wave
+            if (lane0) cross_wave(a, open_k, open_st, en, open_d, c0, per);
+          } else if (open_d == kNoneRel) {
+            pend_lo = open_k;  // = kb - 1, written with the tile's valid strings
+          } else if (lane0) {
+            write_result(a, open_k, data + open_st, en - open_st, open_d);
+          }
+        }
+      } else if (ends) {
+        pend_lo = open_k;  // valid and begun in this wave: written with the tile's valid strings
       }
+      if (ends) open_k = -1;
     }
     // strings that start and end in the tile: with no error anywhere in the tile all are valid
     if (!tile_bad) pend_hi = k1 - 1 > kb ? k1 - 1 : kb;
-    for (int64_t j0 = kb; tile_bad && j0 < k1 - 1; j0 += 64) {
-      const int64_t k = j0 + lane;
+    for (int j0 = kb; tile_bad && j0 < k1 - 1; j0 += 64) {
+      const int k = j0 + lane;
       int64_t st = 0, en = 0;
-      if (cnt < 64) {  // the shuffle reads from every lane: before the branch below
-        st = lane_value(vwin, (int)(k - k0) & 63);
-        en = lane_value(vwin, (int)(k + 1 - k0) & 63);
+      if (!dense) {  // the shuffle reads from every lane: before the branch below
+        st = lane_value(vwin, (k - k0) & 63);
+        en = lane_value(vwin, (k + 1 - k0) & 63);
       }
       if (k < k1 - 1) {
-        if (cnt >= 64) {
+        if (dense) {
           st = boundary(k, offsets, k0, k1, soff);
           en = boundary(k + 1, offsets, k0, k1, soff);
         }
@@ -687,9 +702,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
         write_result(a, k, tile_bytes + (st - ts), en - st, d);
       }
     }
-    if (k1 - 1 >= kb && k1 <= n) {  // the string starting here that runs past te
+    if (k1 - 1 >= kb && k1 <= n32) {  // the string starting here that runs past te
       open_k = k1 - 1;
-      open_st = cnt < 64 ? window_uniform(vwin, open_k, k0) : uniform(boundary(open_k, offsets, k0, k1, soff));
+      open_first = false;
+      open_st = !dense ? window_uniform(vwin, open_k, k0) : uniform(boundary(open_k, offsets, k0, k1, soff));
       open_d = kNoneRel;
       if (tile_bad) {
         const int r = first_bit(regm, nz, (int)(open_st - ts), kTile);
@@ -779,6 +795,7 @@ static int batch_level(const TuneBatch& cfg) {
 
 hipError_t launch_batch(const BatchArgs& a, const TuneBatch& cfg, int num_cus, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
+  if (a.n > kMaxBatchStrings) return hipErrorInvalidValue;
   if (cfg.ascii)
     hipLaunchKernelGGL(batch_main<true>, dim3(batch_grid(cfg, num_cus)), dim3(64), 0, st, a, batch_level(cfg));
   else

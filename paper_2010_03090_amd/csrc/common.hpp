@@ -31,6 +31,9 @@ constexpr int kStateGroups = 64;   // group words under the top word
 constexpr int kStateStride = 32;   // words between state words (256 bytes)
 constexpr int kStateWords = kStateStride * (1 + kStateGroups);
 
+// Strings per batch: the batch kernel counts string indices in 32 bits.
+constexpr int64_t kMaxBatchStrings = (int64_t(1) << 31) - 65;
+
 struct BatchArgs {
   const uint8_t* data;
   const int64_t* offsets;

@@ -133,20 +133,7 @@ namespace {
 
 using namespace utf8v;
 
-int64_t now_ns() {
-  return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
-      .count();
-}
-
-struct Slot {  // one submitted request
-  const uint8_t* data;
-  const int64_t* offsets;
-  int64_t n, bytes;
-  uint8_t* flags;
-  int64_t* errs;
-  int64_t submit_ns, done_ns;
-  std::atomic<int> state{0};  // 0 free, 1 submitted, 2 scheduled, 3 done
-};
+int64_t now_ns() { return mono_ns(); }
 
 struct Staging {  // pinned host image of one batch's descriptor region
   uint8_t* host = nullptr;
@@ -155,10 +142,7 @@ struct Staging {  // pinned host image of one batch's descriptor region
   bool busy = false;
 };
 
-struct InFlight {
-  uint64_t first, count;
-  int staging;
-};
+struct GpuBackend;
 
 }  // namespace
 
@@ -170,25 +154,33 @@ struct utf8v_server {
   uint8_t* ring = nullptr;
   ByteRing alloc{0};
   std::vector<Staging> staging;
-  std::unique_ptr<Slot[]> slots;
-  std::atomic<uint64_t> next_ticket{0};
-  std::atomic<uint64_t> retired{0};  // tickets below this are done
-  uint64_t sched = 0;                // next ticket to schedule
-  std::deque<InFlight> inflight;
-  std::atomic<bool> stop{false};
-  std::atomic<int> error{0};
-  std::thread worker;
   int next_stream = 0;
-  // statistics
-  std::atomic<int64_t> batches{0}, max_batch{0};
-
-  Slot& slot(uint64_t t) { return slots[t % (uint64_t)cfg.max_pending]; }
-  void run();
-  bool launch_batch_of(uint64_t first, uint64_t count);
-  bool retire_ready();
+  std::unique_ptr<GpuBackend> backend;
+  std::unique_ptr<ServeScheduler<GpuBackend>> sched;
+  std::thread worker;
 };
 
 namespace {
+
+// The scheduler's backend: one batch = one ring reservation + one staging buffer, four
+// steps on the next stream, and an event that marks the batch done.
+struct GpuBackend {
+  utf8v_server* s;
+  int launch(uint64_t first, uint64_t count);
+  int query(int h) {
+    const hipError_t q = hipEventQuery(s->staging[(size_t)h].ev);
+    if (q == hipErrorNotReady) return 0;
+    if (q != hipSuccess) {
+      (void)hipGetLastError();
+      return UTF8V_EHIP;
+    }
+    return 1;
+  }
+  void release(int h) {
+    s->staging[(size_t)h].busy = false;
+    s->alloc.release_oldest();
+  }
+};
 
 // Table sizes in the descriptor region of a batch.
 size_t desc_region_bytes(size_t nreq, uint64_t data_bytes, int64_t strings) {
@@ -205,44 +197,21 @@ uint64_t max_footprint(const utf8v_server_config& c) {
          align_up(8 * (sn + 1), kRingAlign) + align_up(sn, kRingAlign) + align_up(8 * sn, kRingAlign);
 }
 
-}  // namespace
-
-bool utf8v_server::retire_ready() {
-  bool any = false;
-  while (!inflight.empty()) {
-    const InFlight& f = inflight.front();
-    const hipError_t q = hipEventQuery(staging[f.staging].ev);
-    if (q == hipErrorNotReady) break;
-    if (q != hipSuccess) {
-      error.store(UTF8V_EHIP);
-      (void)hipGetLastError();
-    }
-    const int64_t t = now_ns();
-    for (uint64_t i = 0; i < f.count; ++i) {
-      Slot& s = slot(f.first + i);
-      s.done_ns = t;
-      s.state.store(3, std::memory_order_release);
-    }
-    retired.store(f.first + f.count, std::memory_order_release);
-    staging[f.staging].busy = false;
-    alloc.release_oldest();
-    inflight.pop_front();
-    any = true;
-  }
-  return any;
-}
-
-// Plan, stage and enqueue tickets [first, first+count) as one batch.  False if the
-// ring or a staging buffer is not free yet (nothing is enqueued then).
-bool utf8v_server::launch_batch_of(uint64_t first, uint64_t count) {
+// Plan, stage and enqueue tickets [first, first+count) as one batch; the staging index
+// is the batch's handle.  -1 if the ring or a staging buffer is not free yet (nothing is
+// enqueued then).
+int GpuBackend::launch(uint64_t first, uint64_t count) {
+  auto& staging = s->staging;
+  auto& alloc = s->alloc;
+  auto slot = [this](uint64_t t) -> const ServeRequest& { return s->sched->slot(t); };
   int si = -1;
   for (size_t i = 0; i < staging.size(); ++i)
     if (!staging[i].busy) { si = (int)i; break; }
-  if (si < 0) return false;
+  if (si < 0) return -1;
   std::vector<PlanRequest> reqs(count);
   for (uint64_t i = 0; i < count; ++i) {
-    const Slot& s = slot(first + i);
-    reqs[i] = PlanRequest{(uint64_t)s.bytes, s.n, reinterpret_cast<uintptr_t>(s.data + s.offsets[0])};
+    const ServeRequest& r = slot(first + i);
+    reqs[i] = PlanRequest{(uint64_t)r.bytes, r.n, reinterpret_cast<uintptr_t>(r.data + r.offsets[0])};
   }
   BatchPlan plan = plan_batch(reqs, 0, count, sizeof(ServeDesc));
   const size_t dbytes = desc_region_bytes(count, plan.data_bytes, plan.strings);
@@ -251,12 +220,12 @@ bool utf8v_server::launch_batch_of(uint64_t first, uint64_t count) {
   plan.data_at += shift; plan.offsets_at += shift; plan.flags_at += shift; plan.errs_at += shift; plan.total += shift;
   Staging& stg = staging[si];
   if (dbytes > stg.cap) {
-    error.store(UTF8V_ENOMEM);
-    return false;
+    s->sched->set_error(UTF8V_ENOMEM);
+    return -1;
   }
   const int64_t at = alloc.reserve(plan.total);
-  if (at < 0) return false;
-  uint8_t* base = ring + at;
+  if (at < 0) return -1;
+  uint8_t* base = s->ring + at;
   // descriptor region image
   ServeDesc* desc = reinterpret_cast<ServeDesc*>(stg.host);
   const size_t chunks = (size_t)((plan.data_bytes + kGatherChunk - 1) / kGatherChunk);
@@ -265,8 +234,8 @@ bool utf8v_server::launch_batch_of(uint64_t first, uint64_t count) {
   int32_t* block_req = reinterpret_cast<int32_t*>(reinterpret_cast<uint8_t*>(chunk_req) +
                                                   align_up(4 * (chunks + 1), 256));
   for (uint64_t i = 0; i < count; ++i) {
-    const Slot& s = slot(first + i);
-    desc[i] = ServeDesc{s.data + s.offsets[0], s.offsets, s.flags, s.errs, s.n, s.bytes,
+    const ServeRequest& r = slot(first + i);
+    desc[i] = ServeDesc{r.data + r.offsets[0], r.offsets, r.flags, r.errs, r.n, r.bytes,
                         (int64_t)plan.data_off[i], plan.str_off[i]};
   }
   {  // first request overlapping each payload chunk / string block
@@ -283,9 +252,9 @@ bool utf8v_server::launch_batch_of(uint64_t first, uint64_t count) {
       block_req[b] = (int32_t)r;
     }
   }
-  hipStream_t st = streams[next_stream];
-  unsigned long long* wslots = wave_slots[next_stream];
-  next_stream = (next_stream + 1) % (int)streams.size();
+  hipStream_t st = s->streams[(size_t)s->next_stream];
+  unsigned long long* wslots = s->wave_slots[(size_t)s->next_stream];
+  s->next_stream = (s->next_stream + 1) % (int)s->streams.size();
   const ServeDesc* ddesc = reinterpret_cast<const ServeDesc*>(base);
   const int32_t* dchunk = reinterpret_cast<const int32_t*>(base + (reinterpret_cast<uint8_t*>(chunk_req) - stg.host));
   const int32_t* dblock = reinterpret_cast<const int32_t*>(base + (reinterpret_cast<uint8_t*>(block_req) - stg.host));
@@ -326,10 +295,10 @@ bool utf8v_server::launch_batch_of(uint64_t first, uint64_t count) {
     utf8v_get_config(&c);
     tb.waves_per_cu = c.batch_waves_per_cu;
     tb.ascii = c.batch_ascii;
-    const Slot& s0 = slot(first);
-    e = utf8v::launch_batch(batch_args(data, offs, plan.strings, direct ? s0.flags : flags,
-                                       direct ? s0.errs : errs, wslots),
-                            tb, cus, st);
+    const ServeRequest& r0 = slot(first);
+    e = utf8v::launch_batch(batch_args(data, offs, plan.strings, direct ? r0.flags : flags,
+                                       direct ? r0.errs : errs, wslots),
+                            tb, s->cus, st);
   }
   if (e == hipSuccess && sblocks > 0 && !direct) {
     if (inline_tables)
@@ -343,52 +312,12 @@ bool utf8v_server::launch_batch_of(uint64_t first, uint64_t count) {
   if (e == hipSuccess) e = hipEventRecord(stg.ev, st);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    error.store(UTF8V_EHIP);
+    s->sched->set_error(UTF8V_EHIP);
     // nothing more runs on this server; the batch is retired when its event reports
   }
   stg.busy = true;
-  for (uint64_t i = 0; i < count; ++i) slot(first + i).state.store(2, std::memory_order_relaxed);
-  inflight.push_back(InFlight{first, count, si});
-  batches.fetch_add(1);
-  int64_t m = max_batch.load();
-  while ((int64_t)count > m && !max_batch.compare_exchange_weak(m, (int64_t)count)) {
-  }
-  return true;
+  return si;
 }
-
-void utf8v_server::run() {
-  (void)hipSetDevice(dev);
-  const uint64_t max_req = (uint64_t)cfg.max_batch_requests;
-  for (;;) {
-    bool progress = retire_ready();
-    if ((int)inflight.size() < cfg.max_inflight) {
-      // admit submitted requests in ticket order up to the batch limits
-      uint64_t count = 0, bytes = 0;
-      int64_t strings = 0;
-      while (count < max_req) {
-        Slot& s = slot(sched + count);
-        if (sched + count >= next_ticket.load(std::memory_order_acquire)) break;
-        if (s.state.load(std::memory_order_acquire) != 1) break;
-        if (count > 0 && (bytes + (uint64_t)s.bytes > cfg.max_batch_bytes ||
-                          strings + s.n + 1 > cfg.max_batch_strings))
-          break;
-        bytes += (uint64_t)s.bytes;
-        strings += s.n + 1;
-        ++count;
-      }
-      if (count > 0 && launch_batch_of(sched, count)) {
-        sched += count;
-        progress = true;
-      }
-    }
-    if (stop.load(std::memory_order_acquire) && inflight.empty() &&
-        sched >= next_ticket.load(std::memory_order_acquire))
-      break;
-    if (!progress) std::this_thread::yield();
-  }
-}
-
-namespace {
 
 thread_local int g_serve_status = UTF8V_OK;
 
@@ -430,7 +359,8 @@ int utf8v_server_default_config(utf8v_server_config* cfg) {
 
 int utf8v_server_create(const utf8v_server_config* cfg, utf8v_server** out) {
   if (!cfg || !out) return UTF8V_EINVAL;
-  if (cfg->max_batch_bytes == 0 || cfg->max_batch_strings < 1 || cfg->max_batch_requests < 1 ||
+  if (cfg->max_batch_bytes == 0 || cfg->max_batch_strings < 1 || cfg->max_batch_strings > kMaxBatchStrings / 2 ||
+      cfg->max_batch_requests < 1 ||
       cfg->max_inflight < 1 || cfg->max_inflight > 64 || cfg->streams < 1 || cfg->streams > 8 ||
       cfg->max_pending < 1 || cfg->budget_bytes < max_footprint(*cfg))
     return UTF8V_EINVAL;
@@ -440,7 +370,11 @@ int utf8v_server_create(const utf8v_server_config* cfg, utf8v_server** out) {
   if (e != hipSuccess) return UTF8V_EHIP;
   s->cus = utf8v_num_cus() > 0 ? utf8v_num_cus() : 1;
   s->alloc = ByteRing(cfg->budget_bytes);
-  s->slots.reset(new Slot[(size_t)cfg->max_pending]);
+  s->backend.reset(new GpuBackend{s.get()});
+  s->sched.reset(new ServeScheduler<GpuBackend>(
+      ServeLimits{cfg->max_batch_bytes, cfg->max_batch_strings, cfg->max_batch_requests, cfg->max_inflight,
+                  cfg->max_pending},
+      s->backend.get()));
   e = hipMalloc(&s->ring, s->alloc.capacity());
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? UTF8V_ENOMEM : UTF8V_EHIP;
   const size_t scap = desc_region_bytes((size_t)cfg->max_batch_requests,
@@ -471,7 +405,10 @@ int utf8v_server_create(const utf8v_server_config* cfg, utf8v_server** out) {
     return UTF8V_EHIP;
   }
   utf8v_server* raw = s.release();
-  raw->worker = std::thread([raw] { raw->run(); });
+  raw->worker = std::thread([raw] {
+    (void)hipSetDevice(raw->dev);
+    raw->sched->run();
+  });
   *out = raw;
   return UTF8V_OK;
 }
@@ -488,53 +425,34 @@ int utf8v_server_submit(utf8v_server* s, const uint8_t* data, const int64_t* off
                                                              !device_accessible(out_first_err))))
     return fail(UTF8V_ENOTDEVICE);
   if ((uint64_t)bytes > s->cfg.max_batch_bytes || n + 1 > s->cfg.max_batch_strings) return fail(UTF8V_EINVAL);
-  if (s->error.load()) return fail(s->error.load());
-  const uint64_t t = s->next_ticket.fetch_add(1);
-  while (t - s->retired.load(std::memory_order_acquire) >= (uint64_t)s->cfg.max_pending) std::this_thread::yield();
-  Slot& sl = s->slot(t);
-  while (sl.state.load(std::memory_order_acquire) == 1 || sl.state.load(std::memory_order_acquire) == 2)
-    std::this_thread::yield();
-  sl.data = data;
-  sl.offsets = offsets;
-  sl.n = n;
-  sl.bytes = bytes;
-  sl.flags = out_flags;
-  sl.errs = out_first_err;
-  sl.submit_ns = now_ns();
-  sl.done_ns = 0;
-  sl.state.store(1, std::memory_order_release);
-  *ticket = t;
+  if (s->sched->error()) return fail(s->sched->error());
+  *ticket = s->sched->submit(data, offsets, n, bytes, out_flags, out_first_err);
   return UTF8V_OK;
 }
 
 int utf8v_server_poll(utf8v_server* s, uint64_t ticket, int64_t* done_ns) {
   if (!s) return UTF8V_EINVAL;
-  if (ticket >= s->retired.load(std::memory_order_acquire)) return s->error.load() ? s->error.load() : 0;
-  if (done_ns) *done_ns = s->slot(ticket).done_ns;
-  return 1;
+  return s->sched->poll(ticket, done_ns);
 }
 
 int utf8v_server_wait(utf8v_server* s, uint64_t ticket, int64_t* done_ns) {
-  if (!s || ticket >= s->next_ticket.load()) return UTF8V_EINVAL;
-  for (;;) {
-    const int r = utf8v_server_poll(s, ticket, done_ns);
-    if (r != 0) return r < 0 ? r : UTF8V_OK;
-    std::this_thread::yield();
-  }
+  if (!s || ticket >= s->sched->submitted()) return UTF8V_EINVAL;
+  const int r = s->sched->wait(ticket, done_ns);
+  return r < 0 ? r : UTF8V_OK;
 }
 
 int utf8v_server_stats(utf8v_server* s, int64_t* out4) {
   if (!s || !out4) return UTF8V_EINVAL;
-  out4[0] = (int64_t)s->retired.load();
-  out4[1] = s->batches.load();
-  out4[2] = s->max_batch.load();
+  out4[0] = (int64_t)s->sched->retired();
+  out4[1] = s->sched->batches();
+  out4[2] = s->sched->max_batch();
   out4[3] = (int64_t)s->alloc.capacity();
   return UTF8V_OK;
 }
 
 int utf8v_server_destroy(utf8v_server* s) {
   if (!s) return UTF8V_EINVAL;
-  s->stop.store(true, std::memory_order_release);
+  if (s->sched) s->sched->stop();
   if (s->worker.joinable()) s->worker.join();
   for (auto st : s->streams) (void)hipStreamSynchronize(st);
   for (auto& st : s->staging) {
@@ -544,7 +462,7 @@ int utf8v_server_destroy(utf8v_server* s) {
   for (auto p : s->wave_slots) (void)hipFree(p);
   for (auto st : s->streams) (void)hipStreamDestroy(st);
   if (s->ring) (void)hipFree(s->ring);
-  const int err = s->error.load();
+  const int err = s->sched ? s->sched->error() : 0;
   delete s;
   return err;
 }

@@ -116,3 +116,17 @@ def test_batch_layout_invariants(shim):
         assert off_at >= data_at + db + 16 and fl_at >= off_at + 8 * (total + 1)
         assert er_at >= fl_at + total and tot >= er_at + 8 * total
         assert all(x % 256 == 0 for x in reg)
+
+
+def test_scheduler_under_thread_sanitizer(tmp_path):
+    """The serving scheduler with a fake backend, several client threads, built with
+    ThreadSanitizer: limits, ticket order, in-order retirement, max_pending backpressure,
+    exactly-once results, and the idle sleep with a late wake-up (tests/serve_sched_check.cpp)."""
+    exe = str(tmp_path / "serve_sched_check")
+    subprocess.check_call(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=thread", "-pthread", "-o", exe,
+                           os.path.join(HERE, "serve_sched_check.cpp")])
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120,
+                       env={**os.environ, "TSAN_OPTIONS": "halt_on_error=1"})
+    assert r.returncode == 0, r.stderr[-3000:]
+    assert "ThreadSanitizer" not in r.stderr, r.stderr[-3000:]
+    assert "scheduler ok" in r.stdout
