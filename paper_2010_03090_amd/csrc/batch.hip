@@ -2,32 +2,38 @@
 //
 // String k is data[offsets[k] .. offsets[k+1]).  Each string is validated as
 // its own stream: the bytes before its start count as zero (as at the start of
-// any input in section 6) and its end gets the end check of section 6.3.  Results: flags[k] = 1 if valid, first_err[k] = start of the
-// first ill-formed character relative to the string start, or -1.
+// any input in section 6) and its end gets the end check of section 6.3.
+// Results: flags[k] = 1 if valid, first_err[k] = start of the first ill-formed
+// character relative to the string start, or -1.
 //
 // One launch does everything.  Work is split by bytes, not by strings: the
 // byte range [offsets[0], offsets[n]] is cut into 4 KiB tiles and a persistent
 // grid of one-wave workgroups gives each wave a contiguous run of tiles, so a
-// 64 MiB string and a million 64-byte strings load-balance alike.
+// 64 MiB string and a million 64-byte strings load-balance alike.  A tile goes
+// from global memory straight into one of the wave's two LDS buffers (the next
+// tile's loads fill the other one while this tile is checked), preceded there by
+// the 16 bytes before it.
 //
-// Per tile the wave first runs the single-buffer checks of section 6 over the tile as
-// plain text (in their short form where the tile holds no byte >= 0xE0), and applies
-// the end check of section 6.3 to the bytes before every string boundary in it.  Where a boundary's end check passes, the string before it
-// ends with a complete character, and then the checks at the boundary and the two
-// positions after it give the same verdict whether or not the bytes of the earlier
-// string are masked to zero; so a tile with neither a plain error nor a failed end
-// check holds only valid strings (the common case, written out directly).  In the 1 KiB
-// slabs of a tile that do hold one, per-position error bits are needed: where no failed
-// end check reaches the slab, the plain checks give them (by the same agreement); the
-// other slabs are checked again per string: a string-start bitmap in LDS, the lookups
-// at position i using prev1/prev2/prev3 only when they belong to the string of i, and
-// each string end getting the end check on its own last bytes.  Lanes that see an
-// error record, per position, a bit in one of two LDS
-// bitmaps (regular error / end-check error).  Then the wave writes the result of
-// every string whose end lies in the tile: its first detection is the first bit in
-// its own range.  A string that runs across tiles carries its first detection in a
-// wave-uniform register; one that runs across waves gets a partial minimum from every
-// wave it touches, in a workspace slot of the wave holding its start, and the last of
+// Per tile the wave first runs the single-buffer checks of section 6 over the tile
+// as plain text (in their short form where the tile holds no byte >= 0xE0), and
+// applies the end check of section 6.3 to the plain bytes before every string
+// boundary in it.  Where the check at a boundary b passes, the string before b ends
+// with a complete character, and then the checks at b, b+1 and b+2 give the same
+// verdict whether or not the bytes before b are masked to zero; at later positions
+// of the string the checks only read the string's own bytes.  So a tile with
+// neither a plain error nor a failed end check holds only valid strings (the
+// common case, written out directly).  Otherwise each string in the tile gets its
+// first detection from three sources: the plain checks in its own range (but not
+// at its first three positions when the check at its start failed), the checks at
+// those three positions with the bytes before its start masked to zero, and the
+// end check of section 6.3 on its own last bytes.  The plain detections are
+// found by checking again only the 16-byte chunks that reported one: the
+// flagged dwords go, in position order, into a short list in LDS, which each
+// string searches for its first detection.
+//
+// A string that runs across tiles carries its first detection in wave-uniform
+// registers; one that runs across waves gets a partial minimum from every wave it
+// touches, in a workspace slot of the wave holding its start, and the last of
 // those waves to arrive (an arrival count kept in the same 64-bit word) writes its
 // result and resets the slot, so the workspace is clean again when the kernel ends.
 #include "common.hpp"
@@ -37,16 +43,21 @@ namespace utf8v {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kU = 4;                       // 1 KiB slabs per wave tile (one per byte lane of the plain check)
+constexpr int kU = 4;                        // 1 KiB slabs per wave tile (one per byte lane of the plain check)
 static_assert(kU == 4, "the plain check transposes four slabs across the byte lanes");
-constexpr int kTile = kU * 1024;            // bytes per tile (one wave)
-constexpr int kMaskPad = 16;                // mask bytes kept before the tile (last 4 used)
-constexpr int kOffCap = 128;                // window boundaries cached in LDS for the error path
+constexpr int kTile = kU * 1024;             // bytes per tile (one wave)
+constexpr int kPad = 16;                     // bytes kept before the tile in its LDS buffer
+constexpr int kBufBytes = kPad + kTile + 16;  // ... and room for reads that run just past its end
+constexpr int kGroupChunks = 16;             // 16-byte chunks checked again per pass (a dword per lane)
+constexpr int32_t kNonePos = INT32_MAX;      // no detection (tile-relative positions)
+constexpr int kNonTemporal = 2;              // cache policy of the tile loads: streamed once
 
-// Pointers to global memory, typed so: every access compiles to a global (not flat)
-// instruction, whose completion an LDS access never has to wait for.
+// Pointers to global memory and LDS, typed so: every access compiles to a global (not
+// flat) instruction, whose completion an LDS access never has to wait for.
 template <class T>
 using gptr = T __attribute__((address_space(1)))*;
+template <class T>
+using lptr = T __attribute__((address_space(3)))*;
 
 struct DevArgs {
   gptr<const uint8_t> data;
@@ -80,6 +91,22 @@ __device__ __forceinline__ gptr<T> sgpr_base(gptr<T> p) {
   return (gptr<T>)v;
 }
 
+// 32-bit value of lane `src` (wave-uniform src).
+__device__ __forceinline__ int32_t lane_at(int32_t v, int src) { return __builtin_amdgcn_readlane(v, src); }
+
+// 64-bit value of lane `src` (wave-uniform src), e.g. boundary k of a window held by the lanes.
+__device__ __forceinline__ int64_t lane_at64(int64_t v, int src) {
+  const uint32_t lo32 = __builtin_amdgcn_readlane((int)(uint32_t)v, src);
+  const uint32_t hi32 = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), src);
+  return (int64_t)(((uint64_t)hi32 << 32) | lo32);
+}
+
+// Lane l gets lane l-1's value (lane 0 gets `first`).
+__device__ __forceinline__ int32_t from_lane_below(int32_t v, int32_t first, int lane) {
+  const int32_t r = __builtin_amdgcn_mov_dpp(v, kDppWaveShr1, 0xF, 0xF, false);
+  return lane == 0 ? first : r;
+}
+
 // Strings [k0, k1) are valid.  Each pass stores 64 results at a wave-uniform base.
 __device__ __forceinline__ void write_valid(const DevArgs& a, int k0, int k1, int lane) {
   k0 = __builtin_amdgcn_readfirstlane(k0);
@@ -109,8 +136,7 @@ __device__ __forceinline__ int64_t logical_wave(int64_t b, int64_t g) {
   return g % kXcds ? b : (b % kXcds) * (g / kXcds) + b / kXcds;
 }
 
-
-// 64-bit value of lane `src` (0..63) of the wave.
+// 64-bit value of lane `src` (0..63, per lane) of the wave.
 __device__ __forceinline__ int64_t lane_value(int64_t x, int src) {
   const int addr = src << 2;
   const uint32_t l = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)x);
@@ -119,19 +145,22 @@ __device__ __forceinline__ int64_t lane_value(int64_t x, int src) {
 }
 
 // k0 = the first k in [0, n] with offsets[k] >= target (offsets[n] >= target is
-// guaranteed by the caller), and v = offsets[k0 + lane] (INT64_MAX past n): the
-// window of boundaries that the wave's first tile scans.  Each round is one
-// dependent load per lane, so the rounds are kept few: the first probes 64 indices
-// 128 apart around the index that the byte position suggests (string lengths are
-// roughly stationary in a batch), leaving about 3000 indices or more on either side;
-// the probe grid is aligned to 2048 indices, so waves with nearby starts read the
-// same cache lines.  When the answer is outside the probes, 64-ary rounds narrow the
-// remaining range; the last round reads the remaining at most 128 indices together
-// with the 64 after them, so the window needs no extra round.
+// guaranteed by the caller), v = offsets[k0 + lane] (INT64_MAX past n): the window
+// of boundaries that the wave's first tile scans, and before = offsets[k0 - 1] (-1
+// when k0 = 0).  Each round is one dependent load per lane, so the rounds are kept
+// few: the first probes 64 indices 128 apart around the index that the byte
+// position suggests (string lengths are roughly stationary in a batch), leaving
+// about 3000 indices or more on either side; the probe grid is aligned to 2048
+// indices, so waves with nearby starts read the same cache lines.  When the answer
+// is outside the probes, 64-ary rounds narrow the remaining range; the last round
+// reads the remaining at most 128 indices together with the 64 after them, so the
+// window needs no extra round.  The value below the range is carried along from the
+// probe that set its lower end.
 __device__ int64_t wave_window(gptr<const int64_t> offsets, int64_t n, int64_t off_lo, int64_t off_hi,
-                               int64_t target, int lane, int64_t& v) {
+                               int64_t target, int lane, int64_t& v, int64_t& before) {
   constexpr int64_t kGap = 128;
   int64_t lo = 0, hi = n;  // the answer lies in [lo, hi]
+  int64_t lo_val = -1;     // offsets[lo - 1] (-1 for lo = 0)
   if (n > kGap) {
     double f = off_hi > off_lo ? (double)(target - off_lo) / (double)(off_hi - off_lo) : 0.0;
     f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
@@ -139,14 +168,20 @@ __device__ int64_t wave_window(gptr<const int64_t> offsets, int64_t n, int64_t o
     g = g < 0 ? 0 : g / 2048 * 2048;
     g = uniform(g > n - 1 ? n - 1 : g);  // first probe, in [0, n)
     const int64_t idx = g + (int64_t)lane * kGap;
-    const int c = __popcll(__ballot(idx < n && offsets[idx] < target));  // probes below target
-    if (c > 0) lo = g + (int64_t)(c - 1) * kGap + 1;
+    const int64_t pv = idx < n ? offsets[idx] : INT64_MAX;
+    const int c = __popcll(__ballot(pv < target));  // probes below target
+    if (c > 0) {
+      lo = g + (int64_t)(c - 1) * kGap + 1;
+      lo_val = lane_at64(pv, c - 1);
+    }
     if (c < 64 && g + (int64_t)c * kGap < n) hi = g + (int64_t)c * kGap;  // that probe is >= target
   }
   while (hi - lo > kGap) {
     const int64_t step = (hi - lo + 63) / 64;
     const int64_t idx = lo + (int64_t)lane * step;
-    const int c = __popcll(__ballot(idx < hi && offsets[idx] < target));
+    const int64_t pv = idx < hi ? offsets[idx] : INT64_MAX;
+    const int c = __popcll(__ballot(pv < target));
+    if (c > 0) lo_val = lane_at64(pv, c - 1);
     const int64_t new_lo = c == 0 ? lo : lo + (int64_t)(c - 1) * step + 1;
     const int64_t new_hi = lo + (int64_t)c * step;
     lo = new_lo;
@@ -163,7 +198,19 @@ __device__ int64_t wave_window(gptr<const int64_t> offsets, int64_t n, int64_t o
   const int src = (lane + r) & 63;
   const int64_t va = lane_value(wa, src), vb = lane_value(wb, src);
   v = lane + r < 64 ? va : vb;
+  if (c > 0) {  // offsets[lo + c - 1]
+    const int cm = c - 1;
+    before = lane_at64(cm < 64 ? w0 : w1, cm & 63);
+  } else {
+    before = lo_val;
+  }
   return lo + c;
+}
+
+// The window of boundaries k .. k+63 (INT64_MAX past n).
+__device__ __forceinline__ int64_t load_window(gptr<const int64_t> offsets, int k, int n32, int lane) {
+  if (k + 63 <= n32) return sgpr_base(offsets + k)[lane];
+  return k + lane <= n32 ? offsets[k + lane] : INT64_MAX;
 }
 
 // The 16-byte chunk at c (16-byte aligned address), loaded only when one of its bytes
@@ -189,93 +236,33 @@ __device__ __forceinline__ u32x4 edge_mask(u32x4 v, int64_t c, int64_t lo, int64
   return u32x4{w[0], w[1], w[2], w[3]};
 }
 
-// Start offset of string k, for k in [k0, n] (LDS when cached).
-__device__ __forceinline__ int64_t boundary(int64_t k, gptr<const int64_t> offsets, int64_t k0, int64_t k1,
-                                            const int64_t* soff) {
-  return (k >= k0 && k < k0 + kOffCap && k < k1) ? soff[k - k0] : offsets[k];
-}
-
-// Boundary k of a window whose cnt < 64 boundaries the lanes hold (lane l: boundary
-// k0 + l): a wave-uniform k is read from its lane, a per-lane k by a lane shuffle, so
-// neither waits on memory.  (A read that may come from either LDS or global memory
-// makes the compiler wait for every outstanding global load, the next tile's included.)
-__device__ __forceinline__ int64_t window_uniform(int64_t vwin, int64_t k, int64_t k0) {
-  const int l = (int)(k - k0);
-  const uint32_t lo32 = __builtin_amdgcn_readlane((int)(uint32_t)vwin, l);
-  const uint32_t hi32 = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)vwin >> 32), l);
-  return (int64_t)(((uint64_t)hi32 << 32) | lo32);
-}
-
-// Loads of one tile: interior tiles read whole chunks (non-temporal); tiles at the
-// edges of the batch range (edge: the tile or the 4 bytes before it reach outside
-// [lo, hi)) read the chunks that hold batch bytes, and batch_mask clears the bytes
-// outside the range (right away, or for a wave's first tile after the boundary search,
-// so the loads stay in flight during it).
-__device__ __forceinline__ void batch_load(u32x4 (&x)[kU], gptr<const uint8_t> data, int64_t ts, int64_t lo,
-                                           int64_t hi, int lane, bool edge) {
-  if (!edge) {
-    const gptr<const u32x4> tile = sgpr_base(reinterpret_cast<gptr<const u32x4>>(data + ts));
+// A tile whose bytes all lie in the batch range: its four 1 KiB slabs go from global
+// memory straight into the LDS buffer (lane l's 16 bytes of slab u to byte
+// kPad + u*1024 + 16*l), read once.
+__device__ __forceinline__ void dma_tile(gptr<const uint8_t> data, int64_t ts, uint8_t* buf, int lane) {
 #pragma unroll
-    for (int u = 0; u < kU; ++u) x[u] = __builtin_nontemporal_load(tile + u * 64 + lane);
-  } else {
-#pragma unroll
-    for (int u = 0; u < kU; ++u) x[u] = edge_load(data, ts + u * 1024 + lane * 16, lo, hi);
-  }
+  for (int u = 0; u < kU; ++u)
+    __builtin_amdgcn_global_load_lds((gptr<const void>)(sgpr_base(data + ts + u * 1024) + lane * 16),
+                                     (lptr<void>)(buf + kPad + u * 1024), 16, 0, kNonTemporal);
 }
 
-__device__ __forceinline__ void batch_mask(u32x4 (&x)[kU], int64_t ts, int64_t lo, int64_t hi, int lane, bool edge) {
-  if (edge) {
+// A tile at an edge of the batch range: the chunks that hold batch bytes are read, the
+// bytes outside [lo, hi) set to zero, and the result stored to the LDS buffer.
+__device__ __forceinline__ void edge_tile(gptr<const uint8_t> data, int64_t ts, int64_t lo, int64_t hi, uint8_t* buf,
+                                          int lane) {
+  u32x4 x[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) x[u] = edge_mask(x[u], ts + u * 1024 + lane * 16, lo, hi);
-  }
+  for (int u = 0; u < kU; ++u) x[u] = edge_load(data, ts + u * 1024 + lane * 16, lo, hi);
+#pragma unroll
+  for (int u = 0; u < kU; ++u)
+    reinterpret_cast<u32x4*>(buf + kPad + u * 1024)[lane] = edge_mask(x[u], ts + u * 1024 + lane * 16, lo, hi);
 }
 
-constexpr int kMaskWords = kTile / 32;       // words of one per-position error bitmap
-
-// Bits q in [a, b) of a 16-bit chunk mask (a and b are clamped to [0, 16]).
-__device__ __forceinline__ uint32_t bit_range(int64_t a, int64_t b) {
+// Bytes q of a 16-bit mask with q in [a, b) (a and b are clamped to [0, 16]).
+__device__ __forceinline__ uint32_t bit_range(int32_t a, int32_t b) {
   const uint32_t lo = (uint32_t)(a < 0 ? 0 : (a > 16 ? 16 : a));
   const uint32_t hi = (uint32_t)(b < 0 ? 0 : (b > 16 ? 16 : b));
   return hi > lo ? ((1u << hi) - 1u) & ~((1u << lo) - 1u) : 0u;
-}
-
-__device__ __forceinline__ bool bit_at(const uint32_t* m, int r) { return (m[r >> 5] >> (r & 31)) & 1u; }
-
-// Which words of a bitmap hold a set bit: bit w of (nz.lo | nz.hi << 64).  Wave-uniform.
-struct WordSummary {
-  uint64_t lo, hi;
-};
-
-__device__ __forceinline__ WordSummary summarize(const uint32_t* m, int lane) {
-  return WordSummary{__ballot(m[lane] != 0u), __ballot(m[lane + 64] != 0u)};
-}
-
-// First word index >= w whose summary bit is set, or kMaskWords.
-__device__ __forceinline__ int next_word(const WordSummary& nz, int w) {
-  if (w < 64) {
-    const uint64_t l = nz.lo & (~0ull << w);
-    if (l) return __builtin_ctzll(l);
-    w = 64;
-  }
-  if (w >= kMaskWords) return kMaskWords;
-  const uint64_t h = nz.hi & (~0ull << (w - 64));
-  return h ? 64 + __builtin_ctzll(h) : kMaskWords;
-}
-
-// First set bit of m among tile positions [a, b) (0 <= a <= b <= kTile), or -1.  Only
-// words flagged in the summary are read: a word strictly inside the range that holds a
-// bit ends the search, so at most the two edge words are read in vain.
-__device__ int first_bit(const uint32_t* m, const WordSummary& nz, int a, int b) {
-  if (a >= b) return -1;
-  const int wb = (b - 1) >> 5;
-  for (int w = next_word(nz, a >> 5); w <= wb; w = next_word(nz, w + 1)) {
-    const int base = w * 32;
-    uint32_t v = m[w];
-    if (a > base) v &= ~0u << (a - base);
-    if (b < base + 32) v &= (1u << (b - base)) - 1u;
-    if (v) return base + __builtin_ctz(v);
-  }
-  return -1;
 }
 
 // One bit per byte of an error dword: bit b set iff byte b is non-zero.
@@ -284,17 +271,36 @@ __device__ __forceinline__ uint32_t nonzero_bytes(uint32_t e) {
   return ((t >> 7) * 0x00204081u) >> 21 & 0xFu;
 }
 
-// First detection d (relative) -> first-error offset s (section 6.3 applied backwards:
-// the latest k in [d-3, d] that does not cut a character), for a string of length
-// len whose bytes are b[0..len) (in global memory or LDS).  The six bytes before d are
-// read at once.
-template <class P>
-__device__ __forceinline__ int64_t resolve_first_error(P b, int64_t len, int64_t d) {
+// Section 6.3 on the plain bytes before tile position r (r >= -2): they end in an
+// incomplete character (last byte >= 0xC0, second-to-last >= 0xE0, third-to-last >= 0xF0).
+__device__ __forceinline__ bool incomplete_before(const uint8_t* tb, int32_t r) {
+  const uint32_t b1 = tb[r - 1], b2 = tb[r - 2], b3 = tb[r - 3];  // read together
+  return (b1 >= 0xC0u) | (b2 >= 0xE0u) | (b3 >= 0xF0u);
+}
+
+// The same check restricted to the string [s, r): its own last bytes only.
+__device__ __forceinline__ bool incomplete_within(const uint8_t* tb, int32_t r, int32_t s) {
+  const uint32_t b1 = tb[r - 1], b2 = tb[r - 2], b3 = tb[r - 3];
+  return (r - 1 >= s && b1 >= 0xC0u) | (r - 2 >= s && b2 >= 0xE0u) | (r - 3 >= s && b3 >= 0xF0u);
+}
+
+// Section 6.1-6.2 at the positions s, s+1, s+2 of a string starting at s, its bytes
+// before s taken as zero: bit j set iff position s+j is flagged.
+__device__ __forceinline__ uint32_t masked_start_flags(const uint8_t* tb, int32_t s) {
+  const uint32_t x = (uint32_t)tb[s] | (uint32_t)tb[s + 1] << 8 | (uint32_t)tb[s + 2] << 16;
+  return nonzero_bytes(position_errors(x, 0u)) & 7u;
+}
+
+// First detection d (relative to the string start) -> first-error offset s (section
+// 6.3 applied backwards: the latest k in [d-3, d] that does not cut a character), for
+// a string of length len whose byte q is byte(q).  The six bytes before d are read at once.
+template <class F>
+__device__ __forceinline__ int64_t resolve_first_error(F byte, int64_t len, int64_t d) {
   uint32_t w[7];  // w[i] = byte d-i (0 outside the string)
 #pragma unroll
   for (int i = 1; i <= 6; ++i) {
     const int64_t q = d - i;
-    w[i] = (q >= 0 && q < len) ? b[q] : 0u;
+    w[i] = (q >= 0 && q < len) ? byte(q) : 0u;
   }
 #pragma unroll
   for (int i = 0; i <= 3; ++i)  // k = d - i
@@ -302,16 +308,35 @@ __device__ __forceinline__ int64_t resolve_first_error(P b, int64_t len, int64_t
   return d;
 }
 
-template <class P>
-__device__ __forceinline__ void write_result(const DevArgs& a, int64_t k, P b, int64_t len, int64_t d) {
+template <class F>
+__device__ __forceinline__ void write_result(const DevArgs& a, int64_t k, F byte, int64_t len, int64_t d) {
   if (d == kNoneRel) {
     a.flags[k] = 1;
     a.first_err[k] = -1;
   } else {
     a.flags[k] = 0;
-    a.first_err[k] = resolve_first_error(b, len, d);
+    a.first_err[k] = resolve_first_error(byte, len, d);
   }
 }
+
+// Bytes of a string starting at st, read from the tile's LDS buffer where they lie in
+// it or in the 16 bytes before it, else from global memory.
+struct StringBytes {
+  gptr<const uint8_t> data;
+  const uint8_t* tb;
+  int64_t st, ts;
+  __device__ uint32_t operator()(int64_t q) const {
+    const int64_t p = st + q;
+    return p >= ts - kPad ? (uint32_t)tb[p - ts] : (uint32_t)data[p];
+  }
+};
+
+// Bytes of a string held in the tile's LDS buffer from tile position s on.
+struct TileBytes {
+  const uint8_t* tb;
+  int32_t s;
+  __device__ uint32_t operator()(int64_t q) const { return tb[s + (int32_t)q]; }
+};
 
 // Wave holding position p (tiles are dealt out in runs of `per`).
 __device__ __forceinline__ int64_t wave_of(int64_t p, int64_t c0, int64_t per) { return (p - c0) / kTile / per; }
@@ -354,58 +379,41 @@ __device__ void cross_wave(const DevArgs& a, int64_t k, int64_t st, int64_t en, 
     const uint64_t prev = old & kSlotMask;
     const uint64_t best = prev > mine ? prev : mine;
     __hip_atomic_exchange(slot, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    write_result(a, k, a.data + st, en - st, best == 0 ? kNoneRel : (int64_t)(kSlotMask - best));
+    const gptr<const uint8_t> s = a.data + st;
+    write_result(a, k, [s](int64_t q) { return (uint32_t)s[q]; }, en - st,
+                 best == 0 ? kNoneRel : (int64_t)(kSlotMask - best));
   }
 }
 
-// The tile's bytes, and the 8 before it, into LDS (sb[kMaskPad + r] = tile byte r).
-__device__ __forceinline__ void stage_tile(uint8_t* sb, const u32x4 (&x)[kU], uint32_t before2, uint32_t before1,
-                                           int lane) {
-#pragma unroll
-  for (int u = 0; u < kU; ++u) reinterpret_cast<u32x4*>(sb + kMaskPad)[u * 64 + lane] = x[u];
-  if (lane == 0) *reinterpret_cast<uint2*>(sb + kMaskPad - 8) = make_uint2(before2, before1);
-  __syncthreads();
-}
+// The 16-byte chunks of a tile that reported a plain error: chunk q (tile position
+// 16q, q = 64u + lane) is bit q of the 256-bit mask m[0..3].  Wave-uniform.
+struct BadChunks {
+  uint64_t m0, m1, m2, m3;
+  // The first chunk q' >= q with q' < q_end, or -1.
+  __device__ __forceinline__ int next(int q, int q_end) const {
+    for (; q < q_end; q = (q & ~63) + 64) {
+      const int u = q >> 6;
+      const uint64_t w = (u == 0 ? m0 : u == 1 ? m1 : u == 2 ? m2 : m3) & (~0ull << (q & 63));
+      if (w) {
+        const int r = (q & ~63) + (int)__builtin_ctzll(w);
+        return r < q_end ? r : -1;
+      }
+    }
+    return -1;
+  }
+};
 
-// The end check of section 6.3 on the (plain) bytes before the string boundary at tile
-// position r >= -4: the slabs whose checks it makes unreliable when it fails (those of
-// positions r, r+1, r+2), else 0.  Boundaries before -2 belong to the previous tile.
-__device__ __forceinline__ uint32_t end_check_slabs(const uint8_t* tile_bytes, int r) {
-  if (r < -2) return 0u;
-  const uint32_t b1 = tile_bytes[r - 1], b2 = tile_bytes[r - 2], b3 = tile_bytes[r - 3];  // read together
-  if ((b1 < 0xC0) & (b2 < 0xE0) & (b3 < 0xF0)) return 0u;
-  return (1u << ((r < 0 ? 0 : r) >> 10)) | (1u << ((r + 2 < kTile ? r + 2 : kTile - 1) >> 10));
-}
-
-// Byte masks (0xFF per set bit) of four start bits.
-__device__ __forceinline__ uint32_t bits_to_bytes(uint32_t nib) { return ((nib * 0x00204081u) & 0x01010101u) * 0xFFu; }
-
-// One wave per workgroup; each wave validates a contiguous run of tiles.  The data
-// and the first boundary offsets of tile t+1 are requested right after tile t's
-// boundary scan, before tile t is classified, so their latency overlaps it.
-//
-// A tile is first checked as plain text (the single-buffer checks, bytes of other
-// strings included), and at every string boundary b in [ts-2, te) the end check of
-// section 6.3 is applied to the plain bytes before b.  Where that check passes, the
-// bytes before b cannot change any check at b, b+1 or b+2 (the previous character is
-// complete), so the plain checks equal the per-string ones there; elsewhere they are
-// the same computation.  A tile with no plain error and no failed boundary check thus
-// holds only valid strings.  In the other tiles, the 1 KiB slabs holding a plain error
-// or a position b..b+2 of a failed check are checked again per string (a string-start
-// bitmap in LDS, the bytes of other strings masked to zero); the remaining slabs have
-// no error under either form.
-// Five waves per SIMD: the kernel fits 96 VGPRs (93, no scratch); left to itself the
-// compiler takes 99 and four waves, which costs the resident-grid launches their
-// priority levels.
+// One wave per workgroup; each wave validates a contiguous run of tiles.  The bytes and
+// the boundary window of tile t+1 are requested right after tile t's boundary scan, so
+// their latency overlaps tile t's checks.  Lane l of a window holds boundary kw + l, the
+// end of string kw + l - 1 and the start of string kw + l.
 template <bool ASCII>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void batch_main(BatchArgs a0, int level) {
+__global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
   const DevArgs a = args_of(a0);
-  __shared__ __align__(16) uint8_t sbytes[kTile + kMaskPad];  // tile positions [-16, kTile)
-  __shared__ uint32_t sbits[kMaskWords + 1];                   // string starts at positions [-32, kTile)
-  __shared__ int64_t soff[kOffCap];                            // offsets[k0 ..] of the window
-  __shared__ uint32_t regm[kMaskWords];                        // regular error at tile position r
-  __shared__ uint32_t endm[kMaskWords];                        // end-check error at tile position r
+  __shared__ __align__(16) uint8_t sbuf[2][kBufBytes];  // tile buffers: the tile at kPad, the 16 bytes before it at 0
+  __shared__ uint32_t sflag[64];                         // flagged dwords of the error path: position | flags << 16
   const int lane = threadIdx.x;
+  const bool lane0 = lane == 0;
   const gptr<const int64_t> offsets = a.offsets;
   const gptr<const uint8_t> data = a.data;
   // the byte range is read on the device, so one launch shape serves any batch
@@ -420,29 +428,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
   if (t64 >= tiles64) return;
   int t = (int)t64;
   const int t_end = (int)(t64 + per < tiles64 ? t64 + per : tiles64);
-  const int64_t wave_lo = c0 + (int64_t)t * kTile;
-  regm[lane] = regm[lane + 64] = 0u;
-  endm[lane] = endm[lane + 64] = 0u;
-  // Tiles whose chunks and the 4 bytes before them lie inside the batch range [lo, hi)
-  // read whole chunks; the others (the first and last tiles of the range) are masked.
-  const int64_t in_first64 = (lo + 4 - c0 + kTile - 1) / kTile;
+  // Interior tiles (all bytes inside [lo, hi)) are loaded straight into LDS; the others
+  // (the first and last tiles of the range) are read chunk by chunk and masked.
+  const int64_t in_first64 = (lo - c0 + kTile - 1) / kTile;
   const int64_t in_last64 = hi - kTile - c0 >= 0 ? (hi - kTile - c0) / kTile : -1;
   const int t_in_first = (int)(in_first64 < tiles64 ? in_first64 : tiles64);
   const int t_in_last = (int)in_last64;
+  const int64_t wave_lo = c0 + (int64_t)t * kTile;
   // the first tile's bytes do not depend on the boundary search: requested before it
-  u32x4 x[kU];
-  const bool edge0 = t < t_in_first || t > t_in_last;
-  batch_load(x, data, wave_lo, lo, hi, lane, edge0);
+  bool edge_cur = t < t_in_first || t > t_in_last;
+  if (!edge_cur) dma_tile(data, wave_lo, sbuf[0], lane);
   const u32x4 before = edge_load(data, wave_lo - 16, lo, hi);  // the 16 bytes before the first tile
   // String indices are 32-bit: a batch holds fewer than 2^31 - 64 strings (the host checks).
   const int n32 = (int)n;
-  int64_t v;
-  int k0 = (int)uniform(wave_window(offsets, n, lo, hi, wave_lo - 4, lane, v));
-  batch_mask(x, wave_lo, lo, hi, lane, edge0);
-  const u32x4 bm = wave_lo - 16 >= lo && wave_lo <= hi ? before : edge_mask(before, wave_lo - 16, lo, hi);
-  uint32_t carry = bm.w;    // the dword before the first tile
-  uint32_t carry2 = bm.z;   // and the one before that
-  const bool lane0 = lane == 0;
+  int64_t v, before_k0;
+  int k0 = (int)uniform(wave_window(offsets, n, lo, hi, wave_lo - 4, lane, v, before_k0));
+  before_k0 = uniform(before_k0);
+  if (lane0)
+    *reinterpret_cast<u32x4*>(sbuf[0]) =
+        wave_lo - 16 >= lo && wave_lo <= hi ? before : edge_mask(before, wave_lo - 16, lo, hi);
   AsciiBackoff ascii;
   // the short form for 1- and 2-byte text, first tested on the wave's fourth tile: a wave
   // of a batch of short mixed strings has few tiles and would pay for a test in half of them
@@ -453,72 +457,67 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
   int open_k = -2;
   bool open_first = true;
   int64_t open_st = 0, open_d = kNoneRel;
-  // strings found valid in the previous tile, written during the next one (see step 2)
+  // strings found valid in the previous tile, written during the next one (see step 3)
   int pend_lo = 0, pend_hi = 0;
+  int b = 0;  // LDS buffer of tile t
 
   PriorityLevelsT<int> levels(level != 0, t, t_end - t);
   for (; t < t_end; ++t) {
     levels.step(t);
     const int64_t ts = c0 + (int64_t)t * kTile;
     const int64_t te = ts + kTile;
-    // 1. boundaries of the window [ts-4, te): [k0, k1), those in [ts, te): [kb, k1).  Lane l
+    uint8_t* const buf = sbuf[b];
+    uint8_t* const nbuf = sbuf[b ^ 1];
+    const uint8_t* const tb = buf + kPad;  // tb[p - ts] = byte p, for p >= ts - kPad
+    // 1. this tile's bytes and boundary window have arrived (requested during the previous tile)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    if (edge_cur) edge_tile(data, ts, lo, hi, buf, lane);
+    // 2. boundaries of the window [ts-4, te): [k0, k1), those in [ts, te): [kb, k1).  Lane l
     // holds boundary k0 + l, as a 32-bit position relative to ts.  A tile inside one string
     // (the window's first boundary lies past it) has none; a tile with 64 or more is dense:
-    // its boundaries are counted window by window, the first kOffCap kept in LDS.
+    // its windows after the first are read in the error path.
     const int32_t rv = tile_rel(v, ts);
-    int cnt = __popcll(__ballot(rv < kTile));
-    int cnt_next = __popcll(__ballot(rv < kTile - 4));
-    int cnt_before = __popcll(__ballot(rv < 0));
-    const bool plain = cnt == 0;
+    const int cnt = __popcll(__ballot(rv < kTile));
+    const int cnt_next = __popcll(__ballot(rv < kTile - 4));
+    const int cnt_before = __popcll(__ballot(rv < 0));
     const bool dense = cnt == 64;
-    if (dense) {
-      soff[lane] = v;
-      for (int kk = k0 + 64;; kk += 64) {
-        const int idx = kk + lane;
-        const int64_t w = idx <= n32 ? offsets[idx] : INT64_MAX;
-        if (kk - k0 + lane < kOffCap) soff[kk - k0 + lane] = w;
-        const int32_t rw = tile_rel(w, ts);
-        const int c = __popcll(__ballot(rw < kTile));
-        cnt += c;
-        cnt_next += __popcll(__ballot(rw < kTile - 4));
-        cnt_before += __popcll(__ballot(rw < 0));
-        if (c < 64) break;
-      }
-    }
     const int k1 = k0 + cnt;
     const int kb = k0 + cnt_before;
-    // a window of at most 63 boundaries is held whole by the lanes: lane l has boundary k0 + l
     const int64_t vwin = v;
-    // 2. the previous tile's valid strings are written here, before tile t+1 is requested: a
-    // load's wait also waits for every store issued before it, so these stores get a tile's
-    // time to complete.  Then request tile t+1 (its window starts at boundary k0 + cnt_next).
-    write_valid(a, pend_lo, pend_hi, lane);
-    u32x4 nx[kU];
-    const int k0n = k0 + cnt_next;
-    if (t + 1 < t_end) {
-      const bool edge1 = t + 1 < t_in_first || t + 1 > t_in_last;
-      batch_load(nx, data, te, lo, hi, lane, edge1);
-      batch_mask(nx, te, lo, hi, lane, edge1);
-      if (!plain) {  // (plain: the same window)
-        if (k0n + 63 <= n32) v = sgpr_base(offsets + k0n)[lane];
-        else v = k0n + lane <= n32 ? offsets[k0n + lane] : INT64_MAX;
-      }
-    }
-    __syncthreads();
     if (open_k == -2) {  // first tile of the wave: the string open at its start began before it
-      open_k = kb - 1;
-      if (open_k >= 0) open_st = uniform(offsets[open_k]);
+      // (its end is the first boundary >= ts; 64 or more empty strings may lie before it)
+      int cb = cnt_before, kbase = k0;
+      int64_t vb = vwin, prevb = before_k0;
+      while (cb == 64) {
+        prevb = lane_at64(vb, 63);
+        kbase += 64;
+        vb = load_window(offsets, kbase, n32, lane);
+        cb = __popcll(__ballot(tile_rel(vb, ts) < 0));
+      }
+      open_k = kbase + cb - 1;
+      open_st = cb > 0 ? lane_at64(vb, cb - 1) : prevb;
     }
-    // 3. the dword before each chunk: lane l-1's last dword (lane 0: lane 63 of the previous slab)
+    // the tile for the checks: each lane's four 16-byte chunks and the dword before each
+    u32x4 x[kU];
     uint32_t prev[kU];
-    const uint32_t before_tile = carry, before2 = carry2;  // bytes [ts-4, ts) and [ts-8, ts-4)
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const uint32_t rot = (uint32_t)__builtin_amdgcn_mov_dpp((int)x[u].w, kDppWaveRor1, 0xF, 0xF, true);
-      prev[u] = lane0 ? carry : rot;
-      carry = rot;
+      x[u] = reinterpret_cast<const u32x4*>(tb + u * 1024)[lane];
+      prev[u] = *reinterpret_cast<const uint32_t*>(tb + u * 1024 + lane * 16 - 4);
     }
-    carry2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)x[kU - 1].z, kDppWaveRor1, 0xF, 0xF, true);
+    // 3. requests for tile t+1 (its bytes, its window: boundaries from k0 + cnt_next on; a
+    // dense tile's comes after its error path), then the previous tile's valid strings: a
+    // load's wait also waits for every store issued before it, so these stores get a
+    // tile's time to complete
+    bool edge_next = false;
+    if (t + 1 < t_end) {
+      edge_next = t + 1 < t_in_first || t + 1 > t_in_last;
+      if (!edge_next) dma_tile(data, te, nbuf, lane);
+      if (!dense && cnt_next > 0) v = load_window(offsets, k0 + cnt_next, n32, lane);
+    }
+    if (lane == 63) *reinterpret_cast<u32x4*>(nbuf) = x[kU - 1];  // the 16 bytes before tile t+1
+    write_valid(a, pend_lo, pend_hi, lane);
+    pend_lo = pend_hi = 0;
     // 4. plain checks; a tile that is all ASCII with an ASCII halo cannot hold an error (6.4)
     bool run = true;
     if (ASCII && ascii.due()) {
@@ -528,7 +527,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
       run = !__all((o & 0x80808080u) == 0);
       ascii.result(!run);
     }
-    // bit u: this lane saw a plain error in slab u; bit 4 + u: a failed end check below reaches slab u
+    // bit u: this lane's chunk of slab u holds a plain error
     uint32_t m = 0;
     if (run) {
       // a tile without bytes >= 0xE0 (nor in the dword before each chunk) takes the short
@@ -552,186 +551,172 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void ba
         m = nonzero_bytes(chunks4_errors(0u, x[0], x[1], x[2], x[3], prev[0], prev[1], prev[2], prev[3]));
       }
     }
-    // 5. the tile's bytes (and the 8 before it) in LDS, for the boundary checks, the per-string
-    // recheck and the resolution
-    const uint8_t* tile_bytes = sbytes + kMaskPad;  // tile_bytes[p - ts] = byte p, for p >= ts - 8
-    if (!plain) {
-      stage_tile(sbytes, x, before2, before_tile, lane);
-      // 6. the end check (6.3) on the plain bytes before every string boundary in [ts-2, te).
-      // A failed check at b leaves the plain checks at b, b+1 and b+2 unreliable: their slabs
-      // are rechecked.
-      if (!dense) {
-        if (lane < cnt) m |= end_check_slabs(tile_bytes, tile_rel(vwin, ts)) << 4;
-      } else {
-        for (int k = k0 + lane; k - lane < k1; k += 64)
-          if (k < k1) m |= end_check_slabs(tile_bytes, (int)(boundary(k, offsets, k0, k1, soff) - ts)) << 4;
+    // 5. the end check (6.3) on the plain bytes before each boundary of the window in [ts-2, te)
+    // (earlier ones belong to the previous tile)
+    const bool pfail = lane < cnt && rv >= -2 && incomplete_before(tb, rv);
+    const bool any_plain = __any(m != 0u);
+    const bool tile_bad = any_plain || __any(pfail);
+    if (!tile_bad && !dense) {
+      // 6. every string that ends in the tile is valid, but for the first detection the
+      // open string may carry; those begun in this wave form [pend_lo, pend_hi), written
+      // during the next tile
+      pend_lo = pend_hi = kb;
+      if (open_k >= 0 && kb < k1) {  // the open string ends here
+        const int64_t en = lane_at64(vwin, cnt_before);
+        if (open_first) {  // it began in an earlier wave
+          if (lane0) cross_wave(a, open_k, open_st, en, open_d, c0, per);
+        } else if (open_d == kNoneRel) {
+          pend_lo = open_k;  // = kb - 1
+        } else if (lane0) {
+          write_result(a, open_k, StringBytes{data, tb, open_st, ts}, en - open_st, open_d);
+        }
+        open_k = -1;
       }
-    }
-    const bool tile_bad = __any(m != 0u);
-    uint32_t slabs = 0;   // bit u: slab u needs per-position error bits (wave-uniform)
-    uint32_t mslabs = 0;  // bit u: ... from the per-string (masked) checks
-    if (tile_bad) {
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        if (__any((m >> u) & 1u)) slabs |= 1u << u;
-        if (__any((m >> (4 + u)) & 1u)) mslabs |= 1u << u;
+      if (k1 - 1 > kb) pend_hi = k1 - 1;  // strings kb .. k1-2 start and end in the tile
+      if (k1 - 1 >= kb && k1 <= n32) {    // the string starting here that runs past te
+        open_k = k1 - 1;
+        open_first = false;
+        open_st = lane_at64(vwin, cnt - 1);
+        open_d = kNoneRel;
       }
-      slabs |= mslabs;
-      if (plain) stage_tile(sbytes, x, before2, before_tile, lane);
-    }
-    // 7. rare: per-position error bits of the failing slabs.  Where no failed end check
-    // reaches a slab, its plain checks are the per-string ones (see above); the others are
-    // checked with the bytes of other strings masked to zero, from a string-start bitmap.
-    WordSummary nz{0, 0};
-    uint32_t bad = 0;  // bit u: this lane wrote error bits for slab u
-    if (tile_bad) {
-      if (mslabs) {
-        sbits[lane] = 0u;
-        sbits[lane + 64] = 0u;
-        if (lane0) sbits[kMaskWords] = 0u;
-        __syncthreads();
-        if (!dense) {
-          if (lane < cnt) {
-            const int r = (int)(vwin - ts) + 32;  // bit index, >= 28
-            atomicOr(&sbits[r >> 5], 1u << (r & 31));
+    } else {
+      // 7. rare: first detections string by string, window by window (a dense tile has
+      // several).  Lane l's string ends at the lane's boundary e and starts at the previous
+      // one s (lane 0: the open string's start, or the last boundary of the previous window).
+      BadChunks bad{0, 0, 0, 0};
+      if (any_plain) bad = BadChunks{__ballot(m & 1u), __ballot(m & 2u), __ballot(m & 4u), __ballot(m & 8u)};
+      int kw = k0;          // boundary of lane 0
+      int32_t e = rv;       // the lane's boundary (tile-relative)
+      bool pf = pfail;      // the end check on the plain bytes before it failed
+      int32_t s_first = (int32_t)(open_st - ts < -(int64_t)kRelFar ? -kRelFar : open_st - ts);
+      bool f_first = false;
+      int next_total = 0;   // boundaries before kTile - 4 over the windows
+      for (int w = 0;; ++w) {
+        if (w > 0) {
+          const int64_t vw = load_window(offsets, kw, n32, lane);
+          e = tile_rel(vw, ts);
+          pf = e >= -2 && e < kTile && incomplete_before(tb, e);
+        }
+        const int cw = __popcll(__ballot(e < kTile));
+        next_total += __popcll(__ballot(e < kTile - 4));
+        const int32_t s = from_lane_below(e, s_first, lane);
+        const bool fs = from_lane_below(pf ? 1 : 0, f_first ? 1 : 0, lane) != 0;
+        const int kl = kw + lane;  // the lane's boundary; its string is kl - 1
+        const bool active = kl >= 1 && kl <= n32 && e >= 0 && s < kTile;
+        int32_t dpos = kNonePos;
+        if (active) {
+          if (pf && e < kTile && e > s && incomplete_within(tb, e, s)) dpos = e;
+          if (fs) {  // s >= -2: positions s .. s+2 with the bytes before s masked
+            const uint32_t f = masked_start_flags(tb, s) & bit_range(-s, (e < kTile ? e : kTile) - s);
+            if (f) dpos = s + (int32_t)__builtin_ctz(f);
           }
-        } else {
-          for (int k = k0 + lane; k - lane < k1; k += 64) {
-            if (k < k1) {
-              const int64_t r = boundary(k, offsets, k0, k1, soff) - ts + 32;  // bit index, >= 28
-              atomicOr(&sbits[r >> 5], 1u << (r & 31));
+        }
+        // plain detections in [a0, b0): the flagged dwords of the chunks that reported one
+        const int32_t a0 = (fs ? s + 3 : s) < 0 ? 0 : (fs ? s + 3 : s);
+        const int32_t b0 = e < kTile ? e : kTile;
+        bool need = any_plain && active && a0 < b0 && dpos >= a0;
+        uint64_t needm = __ballot(need);
+        if (needm) {
+          // the chunks from the first searching string's start to the last one's end
+          const int32_t s_lo = lane_at(s, (int)__builtin_ctzll(needm));
+          int q = (s_lo < 0 ? 0 : s_lo) >> 4;
+          const int q_end = (lane_at(b0, 63 - (int)__builtin_clzll(needm)) + 15) >> 4;
+          for (;;) {
+            int my = -1, nch = 0;
+            for (; nch < kGroupChunks; ++nch) {
+              const int qq = bad.next(q, q_end);
+              if (qq < 0) break;
+              if ((lane >> 2) == nch) my = qq * 16 + (lane & 3) * 4;
+              q = qq + 1;
             }
+            if (nch == 0) break;
+            uint32_t fl = 0;
+            if (my >= 0)
+              fl = nonzero_bytes(position_errors(*reinterpret_cast<const uint32_t*>(tb + my),
+                                                 *reinterpret_cast<const uint32_t*>(tb + my - 4)));
+            const uint64_t fm = __ballot(fl != 0u);
+            if (fm) {
+              if (fl) sflag[__builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0))] =
+                  (uint32_t)my | fl << 16;
+              const int np = __popcll(fm);
+              if (need) {  // the first listed dword with a flagged position >= a0
+                int i = 0, cnt_i = np;
+                while (cnt_i > 0) {
+                  const int h = cnt_i >> 1;
+                  const uint32_t ent = sflag[i + h];
+                  const int32_t last = (int32_t)(ent & 0xFFFFu) + 31 - (int32_t)__builtin_clz(ent >> 16);
+                  if (last < a0) {
+                    i += h + 1;
+                    cnt_i -= h + 1;
+                  } else {
+                    cnt_i = h;
+                  }
+                }
+                if (i < np) {
+                  const uint32_t ent = sflag[i];
+                  const int32_t pos = (int32_t)(ent & 0xFFFFu);
+                  const uint32_t f = (ent >> 16) & bit_range(a0 - pos, 16);
+                  const int32_t p = pos + (int32_t)__builtin_ctz(f);
+                  if (p < b0) {
+                    dpos = p;
+                    need = false;
+                  }
+                }
+              }
+            }
+            // later chunks only matter to strings still searching past them
+            if (!__any(need && b0 > q * 16)) break;
           }
         }
-        __syncthreads();
-      }
-#pragma unroll 1
-      for (int u = 0; u < kU; ++u) {
-        if (((slabs >> u) & 1u) == 0u) continue;  // no plain error and no failed end check in it
-        // the lane's 16 bytes and the dword before them
-        const u32x4 xv = reinterpret_cast<const u32x4*>(tile_bytes)[u * 64 + lane];
-        const uint32_t pv = *reinterpret_cast<const uint32_t*>(tile_bytes + u * 1024 + lane * 16 - 4);
-        uint32_t rbits = 0, ebits = 0;
-        if ((mslabs >> u) & 1u) {
-          const int b = u * 1024 + lane * 16 + 32;  // bit of the lane's first position
-          const uint32_t s16 = (sbits[b >> 5] >> (b & 31)) & 0xFFFFu;
-          const uint32_t sp4 = (b & 31) ? (sbits[b >> 5] >> 12) & 0xFu : sbits[(b >> 5) - 1] >> 28;
-          const uint32_t xs[5] = {pv, xv.x, xv.y, xv.z, xv.w};
-          uint32_t ss[5];
-          ss[0] = bits_to_bytes(sp4);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) ss[j + 1] = bits_to_bytes((s16 >> (4 * j)) & 0xFu);
-          MaskedCarry c = masked_halo(pv, ss[0]);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            uint32_t e = 0, tl = 0;
-            masked_next(xs[j + 1], xs[j], ss[j + 1], ss[j], c, e, tl);
-            rbits |= nonzero_bytes(e) << (4 * j);
-            ebits |= nonzero_bytes(tl) << (4 * j);
-          }
-        } else {
-          Carry c;
-          rbits = nonzero_bytes(errors_first(0u, xv.x, pv, c));
-          rbits |= nonzero_bytes(errors_next(0u, xv.y, xv.x, c)) << 4;
-          rbits |= nonzero_bytes(errors_next(0u, xv.z, xv.y, c)) << 8;
-          rbits |= nonzero_bytes(errors_next(0u, xv.w, xv.z, c)) << 12;
+        // results.  The open string (ending at boundary open_k + 1) is done wave-uniformly:
+        // its start may lie many tiles back.
+        const int ol = open_k >= 0 ? open_k + 1 - kw : -1;  // its lane in this window
+        const bool is_open = lane == ol;
+        if (active && e < kTile && !is_open) {
+          const int64_t d = dpos == kNonePos ? kNoneRel : (int64_t)(dpos - s);
+          write_result(a, kl - 1, TileBytes{tb, s}, e - s, d);
         }
-        if ((rbits | ebits) != 0u) {
-          const int64_t base = ts + u * 1024 + lane * 16;
-          if (base - 1 < lo || base + 16 > hi) {  // chunk at an edge of the batch range
-            // regular bits only at positions in [lo, hi), end-check bits in [lo + 1, hi]
-            rbits &= bit_range(lo - base, hi - base);
-            ebits &= bit_range(lo + 1 - base, hi + 1 - base);
-          }
-          reinterpret_cast<uint16_t*>(regm)[u * 64 + lane] = (uint16_t)rbits;
-          reinterpret_cast<uint16_t*>(endm)[u * 64 + lane] = (uint16_t)ebits;
-          bad |= 1u << u;
-        }
-      }
-      __syncthreads();
-      nz = summarize(regm, lane);
-    }
-    // 8. results of the strings that end in this tile (end positions in [ts, te)); those found
-    // valid form the range [pend_lo, pend_hi), written during the next tile
-    pend_lo = pend_hi = kb;
-    if (open_k >= 0) {  // the string open at ts
-      const bool ends = kb < k1;
-      if (tile_bad || (ends && (open_first || open_d != kNoneRel))) {
-        const int64_t en = !ends ? te
-                           : !dense ? window_uniform(vwin, kb, k0)
-                                    : uniform(boundary(kb, offsets, k0, k1, soff));
-        if (tile_bad) {
-          const int r = first_bit(regm, nz, 0, (int)(en - ts));
-          if (r >= 0 && ts + r - open_st < open_d) open_d = ts + r - open_st;
-          if (ends && bit_at(endm, (int)(en - ts)) && en - open_st < open_d) open_d = en - open_st;
-        }
-        if (ends) {
-          if (open_first) {  // it began in an earlier wave
-            if (lane0) cross_wave(a, open_k, open_st, en, open_d, c0, per);
-          } else if (open_d == kNoneRel) {
-            pend_lo = open_k;  // = kb - 1, written with the tile's valid strings
-          } else if (lane0) {
-            write_result(a, open_k, data + open_st, en - open_st, open_d);
+        if (ol >= 0 && ol < 64) {
+          const int32_t od = lane_at(dpos, ol);
+          if (od != kNonePos && ts + od - open_st < open_d) open_d = ts + od - open_st;
+          const int32_t oe = lane_at(e, ol);
+          if (oe < kTile) {  // it ends here
+            const int64_t en = ts + oe;
+            if (open_first) {
+              if (lane0) cross_wave(a, open_k, open_st, en, open_d, c0, per);
+            } else if (lane0) {
+              write_result(a, open_k, StringBytes{data, tb, open_st, ts}, en - open_st, open_d);
+            }
+            open_k = -1;
           }
         }
-      } else if (ends) {
-        pend_lo = open_k;  // valid and begun in this wave: written with the tile's valid strings
-      }
-      if (ends) open_k = -1;
-    }
-    // strings that start and end in the tile: with no error anywhere in the tile all are valid
-    if (!tile_bad) pend_hi = k1 - 1 > kb ? k1 - 1 : kb;
-    for (int j0 = kb; tile_bad && j0 < k1 - 1; j0 += 64) {
-      const int k = j0 + lane;
-      int64_t st = 0, en = 0;
-      if (!dense) {  // the shuffle reads from every lane: before the branch below
-        st = lane_value(vwin, (k - k0) & 63);
-        en = lane_value(vwin, (k + 1 - k0) & 63);
-      }
-      if (k < k1 - 1) {
-        if (dense) {
-          st = boundary(k, offsets, k0, k1, soff);
-          en = boundary(k + 1, offsets, k0, k1, soff);
+        // the string starting in the tile that runs past te
+        const uint64_t cm = __ballot(active && e >= kTile && !is_open);
+        if (cm) {
+          const int l = (int)__builtin_ctzll(cm);
+          const int32_t so = lane_at(s, l), od = lane_at(dpos, l);
+          open_k = kw + l - 1;
+          open_first = false;
+          open_st = ts + so;
+          open_d = od == kNonePos ? kNoneRel : (int64_t)(od - so);
         }
-        int64_t d = kNoneRel;
-        if (en > st) {
-          const int r = first_bit(regm, nz, (int)(st - ts), (int)(en - ts));
-          if (r >= 0) d = ts + r - st;
-          if (bit_at(endm, (int)(en - ts)) && en - st < d) d = en - st;
-        }
-        write_result(a, k, tile_bytes + (st - ts), en - st, d);
+        if (cw < 64) break;
+        s_first = lane_at(e, 63);
+        f_first = lane_at(pf ? 1 : 0, 63) != 0;
+        kw += 64;
       }
+      if (dense && t + 1 < t_end) v = load_window(offsets, k0 + next_total, n32, lane);
+      k0 += next_total - cnt_next;  // (with the common advance below)
     }
-    if (k1 - 1 >= kb && k1 <= n32) {  // the string starting here that runs past te
-      open_k = k1 - 1;
-      open_first = false;
-      open_st = !dense ? window_uniform(vwin, open_k, k0) : uniform(boundary(open_k, offsets, k0, k1, soff));
-      open_d = kNoneRel;
-      if (tile_bad) {
-        const int r = first_bit(regm, nz, (int)(open_st - ts), kTile);
-        if (r >= 0) open_d = ts + r - open_st;
-      }
-    }
-    // 9. clear the error bits this lane set, once every lane has read them
-    if (tile_bad) {
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        if ((bad >> u) & 1) {
-          reinterpret_cast<uint16_t*>(regm)[u * 64 + lane] = 0;
-          reinterpret_cast<uint16_t*>(endm)[u * 64 + lane] = 0;
-        }
-      }
-    }
-    k0 = k0n;
-#pragma unroll
-    for (int u = 0; u < kU; ++u) x[u] = nx[u];
-    __syncthreads();
+    k0 += cnt_next;
+    edge_cur = edge_next;
+    b ^= 1;
   }
   write_valid(a, pend_lo, pend_hi, lane);
   // the string still open runs into the next wave
   if (open_k >= 0 && lane0) cross_wave(a, open_k, open_st, offsets[open_k + 1], open_d, c0, per);
 }
+
 
 __global__ void offsets_check(const int64_t* __restrict__ offsets, int64_t n, int* bad) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= n; k += (int64_t)gridDim.x * blockDim.x) {

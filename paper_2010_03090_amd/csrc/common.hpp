@@ -10,6 +10,7 @@ namespace utf8v {
 constexpr uint64_t kNone = ~uint64_t(0);          // "no error detected" for 64-bit positions
 constexpr int64_t kNoneRel = INT64_MAX;           // same, for per-string relative offsets
 constexpr int kDppWaveRor1 = 0x13C;               // DPP wave_ror:1 -- lane l reads lane (l-1) mod 64
+constexpr int kDppWaveShr1 = 0x138;               // DPP wave_shr:1 -- lane l reads lane l-1 (l >= 1)
 
 struct TuneSingle {
   int unroll = 4;             // dwordx4 loads in flight per lane (1 KiB per wave each)
