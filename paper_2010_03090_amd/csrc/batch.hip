@@ -91,6 +91,22 @@ __device__ __forceinline__ gptr<T> sgpr_base(gptr<T> p) {
   return (gptr<T>)v;
 }
 
+// A value kept in vector registers (the same in every lane): wave-uniform values the loop
+// rarely needs, so the scalar registers hold those it needs on every tile.
+template <class T>
+__device__ __forceinline__ T in_vgpr(T x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// A wave-uniform 64-bit word of global memory read through the scalar cache: its wait
+// covers scalar and LDS accesses only, never the tile loads in flight.
+__device__ __forceinline__ int64_t scalar_load(gptr<const int64_t> p) {
+  int64_t v;
+  asm volatile("s_load_dwordx2 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(p) : "memory");
+  return v;
+}
+
 // 32-bit value of lane `src` (wave-uniform src).
 __device__ __forceinline__ int32_t lane_at(int32_t v, int src) { return __builtin_amdgcn_readlane(v, src); }
 
@@ -145,43 +161,48 @@ __device__ __forceinline__ int64_t lane_value(int64_t x, int src) {
 }
 
 // k0 = the first k in [0, n] with offsets[k] >= target (offsets[n] >= target is
-// guaranteed by the caller), v = offsets[k0 + lane] (INT64_MAX past n): the window
-// of boundaries that the wave's first tile scans, and before = offsets[k0 - 1] (-1
-// when k0 = 0).  Each round is one dependent load per lane, so the rounds are kept
-// few: the first probes 64 indices 128 apart around the index that the byte
-// position suggests (string lengths are roughly stationary in a batch), leaving
-// about 3000 indices or more on either side; the probe grid is aligned to 2048
-// indices, so waves with nearby starts read the same cache lines.  When the answer
-// is outside the probes, 64-ary rounds narrow the remaining range; the last round
-// reads the remaining at most 128 indices together with the 64 after them, so the
-// window needs no extra round.  The value below the range is carried along from the
-// probe that set its lower end.
-__device__ int64_t wave_window(gptr<const int64_t> offsets, int64_t n, int64_t off_lo, int64_t off_hi,
-                               int64_t target, int lane, int64_t& v, int64_t& before) {
-  constexpr int64_t kGap = 128;
+// guaranteed by the caller) and v = offsets[k0 + lane] (INT64_MAX past n): the window
+// of boundaries that the wave's first tile scans.  Each round is one dependent load per
+// lane, so the rounds are kept few.  The first (first_probe, issued before the wave's
+// first tile is checked, so that its latency overlaps the checks) probes 64 indices 128
+// apart around the index that the byte position suggests (string lengths are roughly
+// stationary in a batch), leaving about 3000 indices or more on either side; the probe
+// grid is aligned to 2048 indices, so waves with nearby starts read the same cache
+// lines.  When the answer is outside the probes, 64-ary rounds narrow the remaining
+// range; the last round reads the remaining at most 128 indices together with the 64
+// after them, so the window needs no extra round.
+constexpr int64_t kGap = 128;
+
+struct Probe {
+  int64_t g;   // first probed index (wave-uniform)
+  int64_t pv;  // offsets[g + 128 * lane] (INT64_MAX past n)
+};
+
+// One unconditional load per lane (indices past n read offsets[n]; wave_window takes
+// them as INT64_MAX).  For n <= kGap the value is not used.
+__device__ __forceinline__ Probe first_probe(gptr<const int64_t> offsets, int64_t n, int64_t off_lo, int64_t off_hi,
+                                             int64_t target, int lane) {
+  double f = off_hi > off_lo ? (double)(target - off_lo) / (double)(off_hi - off_lo) : 0.0;
+  f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+  int64_t g = (int64_t)(f * (double)n) - 3072;
+  g = g < 0 ? 0 : g / 2048 * 2048;
+  g = uniform(g > n - 1 ? n - 1 : g);  // in [0, n)
+  const int64_t idx = g + (int64_t)lane * kGap;
+  return Probe{g, offsets[idx < n ? idx : n]};
+}
+
+__device__ int64_t wave_window(gptr<const int64_t> offsets, int64_t n, int64_t target, int lane, const Probe& pr,
+                               int64_t& v) {
   int64_t lo = 0, hi = n;  // the answer lies in [lo, hi]
-  int64_t lo_val = -1;     // offsets[lo - 1] (-1 for lo = 0)
   if (n > kGap) {
-    double f = off_hi > off_lo ? (double)(target - off_lo) / (double)(off_hi - off_lo) : 0.0;
-    f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
-    int64_t g = (int64_t)(f * (double)n) - 3072;
-    g = g < 0 ? 0 : g / 2048 * 2048;
-    g = uniform(g > n - 1 ? n - 1 : g);  // first probe, in [0, n)
-    const int64_t idx = g + (int64_t)lane * kGap;
-    const int64_t pv = idx < n ? offsets[idx] : INT64_MAX;
-    const int c = __popcll(__ballot(pv < target));  // probes below target
-    if (c > 0) {
-      lo = g + (int64_t)(c - 1) * kGap + 1;
-      lo_val = lane_at64(pv, c - 1);
-    }
-    if (c < 64 && g + (int64_t)c * kGap < n) hi = g + (int64_t)c * kGap;  // that probe is >= target
+    const int c = __popcll(__ballot(pr.g + (int64_t)lane * kGap < n && pr.pv < target));  // probes below target
+    if (c > 0) lo = pr.g + (int64_t)(c - 1) * kGap + 1;
+    if (c < 64 && pr.g + (int64_t)c * kGap < n) hi = pr.g + (int64_t)c * kGap;  // that probe is >= target
   }
   while (hi - lo > kGap) {
     const int64_t step = (hi - lo + 63) / 64;
     const int64_t idx = lo + (int64_t)lane * step;
-    const int64_t pv = idx < hi ? offsets[idx] : INT64_MAX;
-    const int c = __popcll(__ballot(pv < target));
-    if (c > 0) lo_val = lane_at64(pv, c - 1);
+    const int c = __popcll(__ballot(idx < hi && offsets[idx] < target));
     const int64_t new_lo = c == 0 ? lo : lo + (int64_t)(c - 1) * step + 1;
     const int64_t new_hi = lo + (int64_t)c * step;
     lo = new_lo;
@@ -198,12 +219,6 @@ __device__ int64_t wave_window(gptr<const int64_t> offsets, int64_t n, int64_t o
   const int src = (lane + r) & 63;
   const int64_t va = lane_value(wa, src), vb = lane_value(wb, src);
   v = lane + r < 64 ? va : vb;
-  if (c > 0) {  // offsets[lo + c - 1]
-    const int cm = c - 1;
-    before = lane_at64(cm < 64 ? w0 : w1, cm & 63);
-  } else {
-    before = lo_val;
-  }
   return lo + c;
 }
 
@@ -338,8 +353,8 @@ struct TileBytes {
   __device__ uint32_t operator()(int64_t q) const { return tb[s + (int32_t)q]; }
 };
 
-// Wave holding position p (tiles are dealt out in runs of `per`).
-__device__ __forceinline__ int64_t wave_of(int64_t p, int64_t c0, int64_t per) { return (p - c0) / kTile / per; }
+// Wave holding position p (tiles are dealt out in runs of `per`; tile indices are 32-bit).
+__device__ __forceinline__ int wave_of(int64_t p, int64_t c0, int per) { return (int)((p - c0) / kTile) / per; }
 
 // Cross-wave slot word: arrivals in bits 40..63 and, in bits 0..39, the least partial
 // first detection d stored as kSlotMask - d (0 = none; a string is shorter than 2^40 - 1
@@ -354,9 +369,8 @@ constexpr uint64_t kSlotMask = (1ull << kSlotShift) - 1;
 // returns the slot to zero.  Lane 0.  A contribution that does not lower the slot's
 // detection (the usual case: none) is a plain atomic add of one arrival, so the
 // many waves inside one long string do not contend in compare-and-swap loops.
-__device__ void cross_wave(const DevArgs& a, int64_t k, int64_t st, int64_t en, int64_t d, int64_t c0,
-                           int64_t per) {
-  const int64_t ws = wave_of(st, c0, per), we = wave_of(en, c0, per);
+__device__ void cross_wave(const DevArgs& a, int64_t k, int64_t st, int64_t en, int64_t d, int64_t c0, int per) {
+  const int ws = wave_of(st, c0, per), we = wave_of(en, c0, per);
   const gptr<unsigned long long> slot = a.slot + ws;
   const uint64_t mine = d == kNoneRel ? 0 : kSlotMask - (uint64_t)d;
   uint64_t old = 0;
@@ -375,7 +389,7 @@ __device__ void cross_wave(const DevArgs& a, int64_t k, int64_t st, int64_t en, 
     }
   }
   if (!done) old = __hip_atomic_fetch_add(slot, 1ull << kSlotShift, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if ((int64_t)(old >> kSlotShift) + 1 == we - ws + 1) {
+  if ((int)(old >> kSlotShift) + 1 == we - ws + 1) {
     const uint64_t prev = old & kSlotMask;
     const uint64_t best = prev > mine ? prev : mine;
     __hip_atomic_exchange(slot, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -402,6 +416,52 @@ struct BadChunks {
     return -1;
   }
 };
+
+// The single-buffer checks of a tile as plain text: bit u of the result is set when this
+// lane's chunk of slab u holds a flagged position.  A tile that is all ASCII with an
+// ASCII halo cannot hold an error (6.4); a tile without bytes >= 0xE0 (nor in the dword
+// before each chunk) takes the short form of the checks, which flags the same positions.
+template <bool ASCII>
+__device__ __forceinline__ uint32_t plain_check(const u32x4 (&x)[kU], const uint32_t (&prev)[kU], AsciiBackoff& ascii,
+                                                AsciiBackoff& two) {
+  if (ASCII && ascii.due()) {
+    uint32_t o = 0;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) o |= x[u].x | x[u].y | x[u].z | x[u].w | prev[u];
+    const bool all_ascii = __all((o & 0x80808080u) == 0);
+    ascii.result(all_ascii);
+    if (all_ascii) return 0u;
+  }
+  bool short_form = false;
+  if (two.due()) {
+    uint32_t o = 0;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) o |= ge_e0(x[u].x) | ge_e0(x[u].y) | ge_e0(x[u].z) | ge_e0(x[u].w) | ge_e0(prev[u]);
+    short_form = __all((o & 0x80808080u) == 0);
+    two.result(short_form);
+  }
+  uint32_t m = 0;
+  if (short_form) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t e = two_byte_errors(x[u].x, prev[u]) | two_byte_errors(x[u].y, x[u].x) |
+                         two_byte_errors(x[u].z, x[u].y) | two_byte_errors(x[u].w, x[u].z);
+      m |= (e & 0x80808080u) ? 1u << u : 0u;
+    }
+  } else {  // byte lane u of the transposed check's result belongs to slab u
+    m = nonzero_bytes(chunks4_errors(0u, x[0], x[1], x[2], x[3], prev[0], prev[1], prev[2], prev[3]));
+  }
+  return m;
+}
+
+// A lane's four 16-byte chunks of the tile in LDS and the dword before each.
+__device__ __forceinline__ void read_tile(const uint8_t* tb, int lane, u32x4 (&x)[kU], uint32_t (&prev)[kU]) {
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    x[u] = reinterpret_cast<const u32x4*>(tb + u * 1024)[lane];
+    prev[u] = *reinterpret_cast<const uint32_t*>(tb + u * 1024 + lane * 16 - 4);
+  }
+}
 
 // One wave per workgroup; each wave validates a contiguous run of tiles.  The bytes and
 // the boundary window of tile t+1 are requested right after tile t's boundary scan, so
@@ -435,32 +495,73 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
   const int t_in_first = (int)(in_first64 < tiles64 ? in_first64 : tiles64);
   const int t_in_last = (int)in_last64;
   const int64_t wave_lo = c0 + (int64_t)t * kTile;
-  // the first tile's bytes do not depend on the boundary search: requested before it
-  bool edge_cur = t < t_in_first || t > t_in_last;
-  if (!edge_cur) dma_tile(data, wave_lo, sbuf[0], lane);
+  // The first tile's bytes do not depend on the boundary search: they are requested first
+  // (into registers), then the search's first probe, and the tile is checked while the
+  // probe is in flight.
+  const bool edge0 = t < t_in_first || t > t_in_last;
+  u32x4 x[kU];
+  uint32_t prev[kU];
+  if (!edge0) {
+    const gptr<const u32x4> tile = sgpr_base(reinterpret_cast<gptr<const u32x4>>(data + wave_lo));
+#pragma unroll
+    for (int u = 0; u < kU; ++u) x[u] = __builtin_nontemporal_load(tile + u * 64 + lane);
+  } else {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) x[u] = edge_load(data, wave_lo + u * 1024 + lane * 16, lo, hi);
+  }
   const u32x4 before = edge_load(data, wave_lo - 16, lo, hi);  // the 16 bytes before the first tile
-  // String indices are 32-bit: a batch holds fewer than 2^31 - 64 strings (the host checks).
-  const int n32 = (int)n;
-  int64_t v, before_k0;
-  int k0 = (int)uniform(wave_window(offsets, n, lo, hi, wave_lo - 4, lane, v, before_k0));
-  before_k0 = uniform(before_k0);
+  asm volatile("" ::: "memory");
+  Probe pr = first_probe(offsets, n, lo, hi, wave_lo - 4, lane);
+  if (edge0) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) x[u] = edge_mask(x[u], wave_lo + u * 1024 + lane * 16, lo, hi);
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u) reinterpret_cast<u32x4*>(sbuf[0] + kPad + u * 1024)[lane] = x[u];
   if (lane0)
     *reinterpret_cast<u32x4*>(sbuf[0]) =
         wave_lo - 16 >= lo && wave_lo <= hi ? before : edge_mask(before, wave_lo - 16, lo, hi);
+#pragma unroll
+  for (int u = 0; u < kU; ++u) prev[u] = *reinterpret_cast<const uint32_t*>(sbuf[0] + kPad + u * 1024 + lane * 16 - 4);
   AsciiBackoff ascii;
   // the short form for 1- and 2-byte text, first tested on the wave's fourth tile: a wave
   // of a batch of short mixed strings has few tiles and would pay for a test in half of them
   AsciiBackoff two{3, 7};
-  // The string open at the tile start: index, start position and first detection so far.
-  // The one open at the wave start began before the wave (open_first): its result goes
-  // through the cross-wave slot.
-  int open_k = -2;
+  const uint32_t m_first = plain_check<ASCII>(x, prev, ascii, two);
+  asm volatile("" : "+v"(pr.pv) : "v"(m_first));  // the probe's value is used after the check
+  // String indices are 32-bit: a batch holds fewer than 2^31 - 64 strings (the host checks).
+  const int n32 = (int)n;
+  int64_t v;
+  int k0 = (int)uniform(wave_window(offsets, n, wave_lo - 4, lane, pr, v));
+  // The string open at the tile start: index and first detection so far.  The one open at
+  // the wave start began before the wave (open_first): its result goes through the
+  // cross-wave slot.  Its end is the first boundary >= the wave start (64 or more empty
+  // strings may lie before it).
+  int open_k;
+  {
+    int cb = __popcll(__ballot(tile_rel(v, wave_lo) < 0)), kbase = k0;
+    int64_t vb = v;
+    while (cb == 64) {
+      kbase += 64;
+      vb = load_window(offsets, kbase, n32, lane);
+      cb = __popcll(__ballot(tile_rel(vb, wave_lo) < 0));
+    }
+    open_k = kbase + cb - 1;
+  }
+  bool first_tile = true;
+  bool edge_cur = false;  // (the first tile's bytes are in place)
   bool open_first = true;
-  int64_t open_st = 0, open_d = kNoneRel;
+  int64_t open_d = kNoneRel;
+  // The first string of the wave that began before it is handed to the cross-wave slot
+  // after the last tile: the slot's atomic returns a value, and a wait for it in the loop
+  // would also wait for the next tile's loads.
+  int first_k = -1;
+  int64_t first_en = 0, first_d = kNoneRel;
   // strings found valid in the previous tile, written during the next one (see step 3)
   int pend_lo = 0, pend_hi = 0;
   int b = 0;  // LDS buffer of tile t
-
+  const int64_t lo_v = in_vgpr(lo), hi_v = in_vgpr(hi);
+  const int per32 = (int)per;
   PriorityLevelsT<int> levels(level != 0, t, t_end - t);
   for (; t < t_end; ++t) {
     levels.step(t);
@@ -471,7 +572,7 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
     const uint8_t* const tb = buf + kPad;  // tb[p - ts] = byte p, for p >= ts - kPad
     // 1. this tile's bytes and boundary window have arrived (requested during the previous tile)
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    if (edge_cur) edge_tile(data, ts, lo, hi, buf, lane);
+    if (edge_cur) edge_tile(data, ts, lo_v, hi_v, buf, lane);
     // 2. boundaries of the window [ts-4, te): [k0, k1), those in [ts, te): [kb, k1).  Lane l
     // holds boundary k0 + l, as a 32-bit position relative to ts.  A tile inside one string
     // (the window's first boundary lies past it) has none; a tile with 64 or more is dense:
@@ -484,27 +585,8 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
     const int k1 = k0 + cnt;
     const int kb = k0 + cnt_before;
     const int64_t vwin = v;
-    if (open_k == -2) {  // first tile of the wave: the string open at its start began before it
-      // (its end is the first boundary >= ts; 64 or more empty strings may lie before it)
-      int cb = cnt_before, kbase = k0;
-      int64_t vb = vwin, prevb = before_k0;
-      while (cb == 64) {
-        prevb = lane_at64(vb, 63);
-        kbase += 64;
-        vb = load_window(offsets, kbase, n32, lane);
-        cb = __popcll(__ballot(tile_rel(vb, ts) < 0));
-      }
-      open_k = kbase + cb - 1;
-      open_st = cb > 0 ? lane_at64(vb, cb - 1) : prevb;
-    }
     // the tile for the checks: each lane's four 16-byte chunks and the dword before each
-    u32x4 x[kU];
-    uint32_t prev[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      x[u] = reinterpret_cast<const u32x4*>(tb + u * 1024)[lane];
-      prev[u] = *reinterpret_cast<const uint32_t*>(tb + u * 1024 + lane * 16 - 4);
-    }
+    read_tile(tb, lane, x, prev);
     // 3. requests for tile t+1 (its bytes, its window: boundaries from k0 + cnt_next on; a
     // dense tile's comes after its error path), then the previous tile's valid strings: a
     // load's wait also waits for every store issued before it, so these stores get a
@@ -518,38 +600,13 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
     if (lane == 63) *reinterpret_cast<u32x4*>(nbuf) = x[kU - 1];  // the 16 bytes before tile t+1
     write_valid(a, pend_lo, pend_hi, lane);
     pend_lo = pend_hi = 0;
-    // 4. plain checks; a tile that is all ASCII with an ASCII halo cannot hold an error (6.4)
-    bool run = true;
-    if (ASCII && ascii.due()) {
-      uint32_t o = 0;
-#pragma unroll
-      for (int u = 0; u < kU; ++u) o |= x[u].x | x[u].y | x[u].z | x[u].w | prev[u];
-      run = !__all((o & 0x80808080u) == 0);
-      ascii.result(!run);
-    }
-    // bit u: this lane's chunk of slab u holds a plain error
-    uint32_t m = 0;
-    if (run) {
-      // a tile without bytes >= 0xE0 (nor in the dword before each chunk) takes the short
-      // form of the checks: the same positions are non-zero
-      bool short_form = false;
-      if (two.due()) {
-        uint32_t o = 0;
-#pragma unroll
-        for (int u = 0; u < kU; ++u) o |= ge_e0(x[u].x) | ge_e0(x[u].y) | ge_e0(x[u].z) | ge_e0(x[u].w) | ge_e0(prev[u]);
-        short_form = __all((o & 0x80808080u) == 0);
-        two.result(short_form);
-      }
-      if (short_form) {
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const uint32_t e = two_byte_errors(x[u].x, prev[u]) | two_byte_errors(x[u].y, x[u].x) |
-                             two_byte_errors(x[u].z, x[u].y) | two_byte_errors(x[u].w, x[u].z);
-          m |= (e & 0x80808080u) ? 1u << u : 0u;
-        }
-      } else {  // byte lane u of the transposed check's result belongs to slab u
-        m = nonzero_bytes(chunks4_errors(0u, x[0], x[1], x[2], x[3], prev[0], prev[1], prev[2], prev[3]));
-      }
+    // 4. plain checks (the wave's first tile was checked during the boundary search)
+    uint32_t m;
+    if (first_tile) {
+      m = m_first;
+      first_tile = false;
+    } else {
+      m = plain_check<ASCII>(x, prev, ascii, two);
     }
     // 5. the end check (6.3) on the plain bytes before each boundary of the window in [ts-2, te)
     // (earlier ones belong to the previous tile)
@@ -564,11 +621,14 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
       if (open_k >= 0 && kb < k1) {  // the open string ends here
         const int64_t en = lane_at64(vwin, cnt_before);
         if (open_first) {  // it began in an earlier wave
-          if (lane0) cross_wave(a, open_k, open_st, en, open_d, c0, per);
+          first_k = open_k;
+          first_en = en;
+          first_d = open_d;
         } else if (open_d == kNoneRel) {
           pend_lo = open_k;  // = kb - 1
         } else if (lane0) {
-          write_result(a, open_k, StringBytes{data, tb, open_st, ts}, en - open_st, open_d);
+          const int64_t st = scalar_load(offsets + open_k);
+          write_result(a, open_k, StringBytes{data, tb, st, ts}, en - st, open_d);
         }
         open_k = -1;
       }
@@ -576,7 +636,6 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
       if (k1 - 1 >= kb && k1 <= n32) {    // the string starting here that runs past te
         open_k = k1 - 1;
         open_first = false;
-        open_st = lane_at64(vwin, cnt - 1);
         open_d = kNoneRel;
       }
     } else {
@@ -584,11 +643,11 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
       // several).  Lane l's string ends at the lane's boundary e and starts at the previous
       // one s (lane 0: the open string's start, or the last boundary of the previous window).
       BadChunks bad{0, 0, 0, 0};
-      if (any_plain) bad = BadChunks{__ballot(m & 1u), __ballot(m & 2u), __ballot(m & 4u), __ballot(m & 8u)};
+      if (any_plain) bad = BadChunks{in_vgpr(__ballot(m & 1u)), in_vgpr(__ballot(m & 2u)), in_vgpr(__ballot(m & 4u)), in_vgpr(__ballot(m & 8u))};
       int kw = k0;          // boundary of lane 0
       int32_t e = rv;       // the lane's boundary (tile-relative)
       bool pf = pfail;      // the end check on the plain bytes before it failed
-      int32_t s_first = (int32_t)(open_st - ts < -(int64_t)kRelFar ? -kRelFar : open_st - ts);
+      int32_t s_first = -kRelFar;  // (window 0: lane 0's string is the open one or ended before ts)
       bool f_first = false;
       int next_total = 0;   // boundaries before kTile - 4 over the windows
       for (int w = 0;; ++w) {
@@ -678,14 +737,19 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
         }
         if (ol >= 0 && ol < 64) {
           const int32_t od = lane_at(dpos, ol);
-          if (od != kNonePos && ts + od - open_st < open_d) open_d = ts + od - open_st;
           const int32_t oe = lane_at(e, ol);
-          if (oe < kTile) {  // it ends here
+          const bool ends = oe < kTile;
+          int64_t st = 0;
+          if (od != kNonePos || (ends && !open_first && open_d != kNoneRel)) st = scalar_load(offsets + open_k);
+          if (od != kNonePos && ts + od - st < open_d) open_d = ts + od - st;
+          if (ends) {  // it ends here
             const int64_t en = ts + oe;
             if (open_first) {
-              if (lane0) cross_wave(a, open_k, open_st, en, open_d, c0, per);
+              first_k = open_k;
+              first_en = en;
+              first_d = open_d;
             } else if (lane0) {
-              write_result(a, open_k, StringBytes{data, tb, open_st, ts}, en - open_st, open_d);
+              write_result(a, open_k, StringBytes{data, tb, st, ts}, en - st, open_d);
             }
             open_k = -1;
           }
@@ -697,7 +761,6 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
           const int32_t so = lane_at(s, l), od = lane_at(dpos, l);
           open_k = kw + l - 1;
           open_first = false;
-          open_st = ts + so;
           open_d = od == kNonePos ? kNoneRel : (int64_t)(od - so);
         }
         if (cw < 64) break;
@@ -714,7 +777,8 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
   }
   write_valid(a, pend_lo, pend_hi, lane);
   // the string still open runs into the next wave
-  if (open_k >= 0 && lane0) cross_wave(a, open_k, open_st, offsets[open_k + 1], open_d, c0, per);
+  if (first_k >= 0 && lane0) cross_wave(a, first_k, offsets[first_k], first_en, first_d, c0, per32);
+  if (open_k >= 0 && lane0) cross_wave(a, open_k, offsets[open_k], offsets[open_k + 1], open_d, c0, per32);
 }
 
 
