@@ -99,14 +99,6 @@ __device__ __forceinline__ T in_vgpr(T x) {
   return x;
 }
 
-// A wave-uniform 64-bit word of global memory read through the scalar cache: its wait
-// covers scalar and LDS accesses only, never the tile loads in flight.
-__device__ __forceinline__ int64_t scalar_load(gptr<const int64_t> p) {
-  int64_t v;
-  asm volatile("s_load_dwordx2 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(p) : "memory");
-  return v;
-}
-
 // 32-bit value of lane `src` (wave-uniform src).
 __device__ __forceinline__ int32_t lane_at(int32_t v, int src) { return __builtin_amdgcn_readlane(v, src); }
 
@@ -353,8 +345,50 @@ struct TileBytes {
   __device__ uint32_t operator()(int64_t q) const { return tb[s + (int32_t)q]; }
 };
 
-// Wave holding position p (tiles are dealt out in runs of `per`; tile indices are 32-bit).
-__device__ __forceinline__ int wave_of(int64_t p, int64_t c0, int per) { return (int)((p - c0) / kTile) / per; }
+// The runs of tiles of the waves: logical wave l gets tiles [begin(l), begin(l+1)).  With
+// rank weights w (byte r = weight of dispatch rank r, non-zero) the runs follow the
+// weights of the waves' ranks: the waves of a SIMD are dispatched one after the other,
+// workgroup b being the (4b / grid)-th of its SIMD in a grid of four waves per SIMD, and
+// a SIMD issues from its oldest wave first, so the younger waves are given shorter runs.
+// Logical wave l = x * grid/8 + j (XCD x) holds workgroup 8j + x, of rank j / (grid/32).
+// Without weights the runs are `per` tiles each.
+struct TileRuns {
+  int64_t tiles, per;
+  int grid;
+  uint32_t w;
+  __device__ int64_t weight(int r) const { return (w >> (8 * r)) & 255u; }
+  // Total weight of the waves before logical wave l (the weights of a wave's rank).
+  __device__ int64_t prefix(int64_t l) const {
+    const int64_t q = grid / 32, x = l / (grid / 8), j = l % (grid / 8), r = j / q, rem = j % q;
+    int64_t p = x * q * (weight(0) + weight(1) + weight(2) + weight(3)) + rem * weight((int)r);
+    for (int k = 0; k < (int)r; ++k) p += q * weight(k);
+    return p;
+  }
+  __device__ int64_t total() const { return (int64_t)grid / 4 * (weight(0) + weight(1) + weight(2) + weight(3)); }
+  __device__ int64_t begin(int64_t l) const {
+    if (w == 0) {
+      const int64_t b = l * per;
+      return b < tiles ? b : tiles;
+    }
+    return tiles * prefix(l) / total();  // below 2^31 * 2^20
+  }
+  // The wave whose run holds tile `tile` (< tiles): the last l with begin(l) <= tile, i.e.
+  // the first l with prefix(l) >= ceil((tile + 1) * total / tiles), less one.
+  __device__ int wave_of_tile(int64_t tile) const {
+    if (w == 0) return (int)(tile / per);
+    const int64_t q = grid / 32, sum = weight(0) + weight(1) + weight(2) + weight(3);
+    const int64_t pp = ((tile + 1) * total() + tiles - 1) / tiles - 1;  // first l with prefix(l) > pp
+    const int64_t x = pp / (q * sum), in_x = pp - x * q * sum;
+    int r = 0;
+    int64_t c = 0;  // weight of the ranks before r within the XCD's part
+    while (r < 3 && in_x >= c + q * weight(r)) {
+      c += q * weight(r);
+      ++r;
+    }
+    return (int)(x * (grid / 8) + r * q + (in_x - c) / weight(r));
+  }
+  __device__ int wave_of(int64_t p, int64_t c0) const { return wave_of_tile((p - c0) / kTile); }
+};
 
 // Cross-wave slot word: arrivals in bits 40..63 and, in bits 0..39, the least partial
 // first detection d stored as kSlotMask - d (0 = none; a string is shorter than 2^40 - 1
@@ -364,39 +398,59 @@ __device__ __forceinline__ int wave_of(int64_t p, int64_t c0, int per) { return 
 constexpr int kSlotShift = 40;
 constexpr uint64_t kSlotMask = (1ull << kSlotShift) - 1;
 
-// String k runs across waves ws < we; this wave contributes the first detection d it
-// saw in its part (kNoneRel if none).  The last contributor writes the result and
-// returns the slot to zero.  Lane 0.  A contribution that does not lower the slot's
-// detection (the usual case: none) is a plain atomic add of one arrival, so the
-// many waves inside one long string do not contend in compare-and-swap loops.
-__device__ void cross_wave(const DevArgs& a, int64_t k, int64_t st, int64_t en, int64_t d, int64_t c0, int per) {
-  const int ws = wave_of(st, c0, per), we = wave_of(en, c0, per);
-  const gptr<unsigned long long> slot = a.slot + ws;
-  const uint64_t mine = d == kNoneRel ? 0 : kSlotMask - (uint64_t)d;
-  uint64_t old = 0;
-  bool done = false;
-  if (mine != 0) {
-    old = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while ((old & kSlotMask) < mine) {
-      const uint64_t nw = (old & ~kSlotMask) + (1ull << kSlotShift) + mine;
+// String k runs across waves ws < we; each of them contributes once the first detection d
+// it saw in its part (kNoneRel if none), and the last to arrive writes the result and
+// returns the slot to zero.  A contribution that does not lower the slot's detection
+// (the usual case: none) is a plain atomic add of one arrival, so the many waves inside
+// one long string do not contend in compare-and-swap loops.  A wave contributes for at
+// most two strings (the one open at its start and the one open at its end), after its
+// last tile; the two arrivals are in flight together.  Lane 0.
+struct CrossWave {
+  int64_t k, st, en, d;
+  int ws, we;
+  uint64_t mine, old;
+};
+
+__device__ __forceinline__ CrossWave cross_wave_begin(int64_t k, int64_t st, int64_t en, int64_t d, int64_t c0,
+                                                      const TileRuns& runs) {
+  CrossWave c{k, st, en, d, 0, 0, 0, 0};
+  if (k >= 0) {
+    c.ws = runs.wave_of(st, c0);
+    c.we = runs.wave_of(en, c0);
+    c.mine = d == kNoneRel ? 0 : kSlotMask - (uint64_t)d;
+  }
+  return c;
+}
+
+// The arrival: an atomic add, or (lowering the detection) a compare-and-swap loop.
+__device__ __forceinline__ void cross_wave_arrive(const DevArgs& a, CrossWave& c, bool lowering) {
+  if (c.k < 0 || (c.mine != 0) != lowering) return;
+  const gptr<unsigned long long> slot = a.slot + c.ws;
+  if (c.mine != 0) {
+    uint64_t old = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while ((old & kSlotMask) < c.mine) {
+      const uint64_t nw = (old & ~kSlotMask) + (1ull << kSlotShift) + c.mine;
       unsigned long long seen = old;
       if (__hip_atomic_compare_exchange_strong(slot, &seen, (unsigned long long)nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT)) {
-        done = true;
-        break;
+        c.old = old;
+        return;
       }
       old = seen;
     }
+    c.mine = 0;  // does not lower it: a plain arrival
   }
-  if (!done) old = __hip_atomic_fetch_add(slot, 1ull << kSlotShift, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if ((int)(old >> kSlotShift) + 1 == we - ws + 1) {
-    const uint64_t prev = old & kSlotMask;
-    const uint64_t best = prev > mine ? prev : mine;
-    __hip_atomic_exchange(slot, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const gptr<const uint8_t> s = a.data + st;
-    write_result(a, k, [s](int64_t q) { return (uint32_t)s[q]; }, en - st,
-                 best == 0 ? kNoneRel : (int64_t)(kSlotMask - best));
-  }
+  c.old = __hip_atomic_fetch_add(slot, 1ull << kSlotShift, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void cross_wave_end(const DevArgs& a, const CrossWave& c) {
+  if (c.k < 0 || (int)(c.old >> kSlotShift) + 1 != c.we - c.ws + 1) return;
+  const uint64_t prev = c.old & kSlotMask;
+  const uint64_t best = prev > c.mine ? prev : c.mine;
+  __hip_atomic_exchange(a.slot + c.ws, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const gptr<const uint8_t> s = a.data + c.st;
+  write_result(a, c.k, [s](int64_t q) { return (uint32_t)s[q]; }, c.en - c.st,
+               best == 0 ? kNoneRel : (int64_t)(kSlotMask - best));
 }
 
 // The 16-byte chunks of a tile that reported a plain error: chunk q (tile position
@@ -468,7 +522,7 @@ __device__ __forceinline__ void read_tile(const uint8_t* tb, int lane, u32x4 (&x
 // their latency overlaps tile t's checks.  Lane l of a window holds boundary kw + l, the
 // end of string kw + l - 1 and the start of string kw + l.
 template <bool ASCII>
-__global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
+__global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level, uint32_t rank_weights) {
   const DevArgs a = args_of(a0);
   __shared__ __align__(16) uint8_t sbuf[2][kBufBytes];  // tile buffers: the tile at kPad, the 16 bytes before it at 0
   __shared__ uint32_t sflag[64];                         // flagged dwords of the error path: position | flags << 16
@@ -483,11 +537,13 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
   // tiles cover [c0, hi]: position hi holds the end check of the last string.  Tile
   // indices are 32-bit (a batch range below 8 TiB), so the loop's comparisons stay scalar.
   const int64_t tiles64 = (hi + 1 - c0 + kTile - 1) / kTile;
-  const int64_t per = (tiles64 + gridDim.x - 1) / gridDim.x;
-  const int64_t t64 = logical_wave(blockIdx.x, gridDim.x) * per;
-  if (t64 >= tiles64) return;
+  const TileRuns runs{tiles64, (tiles64 + gridDim.x - 1) / gridDim.x, (int)gridDim.x,
+                      gridDim.x % 32 == 0 ? rank_weights : 0u};
+  const int64_t lw = logical_wave(blockIdx.x, gridDim.x);
+  const int64_t t64 = runs.begin(lw), t_end64 = runs.begin(lw + 1);
+  if (t64 >= t_end64) return;
   int t = (int)t64;
-  const int t_end = (int)(t64 + per < tiles64 ? t64 + per : tiles64);
+  const int t_end = (int)t_end64;
   // Interior tiles (all bytes inside [lo, hi)) are loaded straight into LDS; the others
   // (the first and last tiles of the range) are read chunk by chunk and masked.
   const int64_t in_first64 = (lo - c0 + kTile - 1) / kTile;
@@ -548,6 +604,9 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
     }
     open_k = kbase + cb - 1;
   }
+  // Start of the open string, held in vector registers (the same in every lane): the
+  // scalar registers are kept for what every tile needs.
+  int64_t open_st_v = open_k >= 0 ? offsets[open_k] : 0;
   bool first_tile = true;
   bool edge_cur = false;  // (the first tile's bytes are in place)
   bool open_first = true;
@@ -556,12 +615,13 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
   // after the last tile: the slot's atomic returns a value, and a wait for it in the loop
   // would also wait for the next tile's loads.
   int first_k = -1;
-  int64_t first_en = 0, first_d = kNoneRel;
+  int64_t first_en_v = 0, first_d_v = kNoneRel, first_st_v = 0;
+  int64_t final_en_v = 0;  // end of the string open after the last tile
   // strings found valid in the previous tile, written during the next one (see step 3)
   int pend_lo = 0, pend_hi = 0;
   int b = 0;  // LDS buffer of tile t
-  const int64_t lo_v = in_vgpr(lo), hi_v = in_vgpr(hi);
-  const int per32 = (int)per;
+  const int64_t lo_v = in_vgpr(lo), hi_v = in_vgpr(hi), tiles_v = in_vgpr(tiles64);
+  const uint32_t weights_v = in_vgpr(runs.w);
   PriorityLevelsT<int> levels(level != 0, t, t_end - t);
   for (; t < t_end; ++t) {
     levels.step(t);
@@ -585,6 +645,7 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
     const int k1 = k0 + cnt;
     const int kb = k0 + cnt_before;
     const int64_t vwin = v;
+    if (t + 1 == t_end && !dense) final_en_v = in_vgpr(lane_at64(vwin, cnt));  // first boundary >= te
     // the tile for the checks: each lane's four 16-byte chunks and the dword before each
     read_tile(tb, lane, x, prev);
     // 3. requests for tile t+1 (its bytes, its window: boundaries from k0 + cnt_next on; a
@@ -622,12 +683,13 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
         const int64_t en = lane_at64(vwin, cnt_before);
         if (open_first) {  // it began in an earlier wave
           first_k = open_k;
-          first_en = en;
-          first_d = open_d;
+          first_en_v = in_vgpr(en);
+          first_d_v = in_vgpr(open_d);
+          first_st_v = open_st_v;
         } else if (open_d == kNoneRel) {
           pend_lo = open_k;  // = kb - 1
         } else if (lane0) {
-          const int64_t st = scalar_load(offsets + open_k);
+          const int64_t st = uniform(open_st_v);
           write_result(a, open_k, StringBytes{data, tb, st, ts}, en - st, open_d);
         }
         open_k = -1;
@@ -637,6 +699,7 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
         open_k = k1 - 1;
         open_first = false;
         open_d = kNoneRel;
+        open_st_v = in_vgpr(lane_at64(vwin, cnt - 1));
       }
     } else {
       // 7. rare: first detections string by string, window by window (a dense tile has
@@ -645,15 +708,16 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
       BadChunks bad{0, 0, 0, 0};
       if (any_plain) bad = BadChunks{in_vgpr(__ballot(m & 1u)), in_vgpr(__ballot(m & 2u)), in_vgpr(__ballot(m & 4u)), in_vgpr(__ballot(m & 8u))};
       int kw = k0;          // boundary of lane 0
-      int32_t e = rv;       // the lane's boundary (tile-relative)
+      int64_t vcur = vwin;  // the lane's boundary
+      int32_t e = rv;       // ... tile-relative
       bool pf = pfail;      // the end check on the plain bytes before it failed
       int32_t s_first = -kRelFar;  // (window 0: lane 0's string is the open one or ended before ts)
       bool f_first = false;
       int next_total = 0;   // boundaries before kTile - 4 over the windows
       for (int w = 0;; ++w) {
         if (w > 0) {
-          const int64_t vw = load_window(offsets, kw, n32, lane);
-          e = tile_rel(vw, ts);
+          vcur = load_window(offsets, kw, n32, lane);
+          e = tile_rel(vcur, ts);
           pf = e >= -2 && e < kTile && incomplete_before(tb, e);
         }
         const int cw = __popcll(__ballot(e < kTile));
@@ -739,15 +803,15 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
           const int32_t od = lane_at(dpos, ol);
           const int32_t oe = lane_at(e, ol);
           const bool ends = oe < kTile;
-          int64_t st = 0;
-          if (od != kNonePos || (ends && !open_first && open_d != kNoneRel)) st = scalar_load(offsets + open_k);
+          const int64_t st = uniform(open_st_v);
           if (od != kNonePos && ts + od - st < open_d) open_d = ts + od - st;
           if (ends) {  // it ends here
             const int64_t en = ts + oe;
             if (open_first) {
               first_k = open_k;
-              first_en = en;
-              first_d = open_d;
+              first_en_v = in_vgpr(en);
+              first_d_v = in_vgpr(open_d);
+              first_st_v = open_st_v;
             } else if (lane0) {
               write_result(a, open_k, StringBytes{data, tb, st, ts}, en - st, open_d);
             }
@@ -762,8 +826,12 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
           open_k = kw + l - 1;
           open_first = false;
           open_d = od == kNonePos ? kNoneRel : (int64_t)(od - so);
+          open_st_v = in_vgpr(ts + so);
         }
-        if (cw < 64) break;
+        if (cw < 64) {
+          if (t + 1 == t_end && dense) final_en_v = in_vgpr(lane_at64(vcur, cw));  // first boundary >= te
+          break;
+        }
         s_first = lane_at(e, 63);
         f_first = lane_at(pf ? 1 : 0, 63) != 0;
         kw += 64;
@@ -776,9 +844,21 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
     b ^= 1;
   }
   write_valid(a, pend_lo, pend_hi, lane);
-  // the string still open runs into the next wave
-  if (first_k >= 0 && lane0) cross_wave(a, first_k, offsets[first_k], first_en, first_d, c0, per32);
-  if (open_k >= 0 && lane0) cross_wave(a, open_k, offsets[open_k], offsets[open_k + 1], open_d, c0, per32);
+  // the strings that run across waves: the one open at the wave start that ended in it,
+  // and the one still open, which runs into the next wave
+  if (lane0 && (first_k >= 0 || open_k >= 0)) {
+    const int64_t tiles_u = uniform(tiles_v);
+    const TileRuns runs_u{tiles_u, (tiles_u + gridDim.x - 1) / gridDim.x, (int)gridDim.x,
+                          (uint32_t)__builtin_amdgcn_readfirstlane(weights_v)};
+    CrossWave c1 = cross_wave_begin(first_k, uniform(first_st_v), uniform(first_en_v), uniform(first_d_v), c0, runs_u);
+    CrossWave c2 = cross_wave_begin(open_k, uniform(open_st_v), uniform(final_en_v), open_d, c0, runs_u);
+    cross_wave_arrive(a, c1, false);
+    cross_wave_arrive(a, c2, false);
+    cross_wave_arrive(a, c1, true);
+    cross_wave_arrive(a, c2, true);
+    cross_wave_end(a, c1);
+    cross_wave_end(a, c2);
+  }
 }
 
 
@@ -838,6 +918,15 @@ static int batch_grid(const TuneBatch& cfg, int num_cus) {
   return num_cus * (cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1);
 }
 
+// Rank weights of the tile runs: only for a grid of exactly four resident waves per SIMD,
+// whose waves all start together, the youngest of each SIMD last.
+static uint32_t batch_weights(const TuneBatch& cfg, int num_cus) {
+  return cfg.waves_per_cu == 16 && batch_grid(cfg, num_cus) % 32 == 0 &&
+                 cfg.waves_per_cu <= resident_waves_per_cu(cfg.ascii != 0)
+             ? cfg.rank_weights
+             : 0u;
+}
+
 static int batch_level(const TuneBatch& cfg) {
   return (cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1) <= resident_waves_per_cu(cfg.ascii != 0) ? 1 : 0;
 }
@@ -846,9 +935,11 @@ hipError_t launch_batch(const BatchArgs& a, const TuneBatch& cfg, int num_cus, h
   if (a.n <= 0) return hipSuccess;
   if (a.n > kMaxBatchStrings) return hipErrorInvalidValue;
   if (cfg.ascii)
-    hipLaunchKernelGGL(batch_main<true>, dim3(batch_grid(cfg, num_cus)), dim3(64), 0, st, a, batch_level(cfg));
+    hipLaunchKernelGGL(batch_main<true>, dim3(batch_grid(cfg, num_cus)), dim3(64), 0, st, a, batch_level(cfg),
+                       batch_weights(cfg, num_cus));
   else
-    hipLaunchKernelGGL(batch_main<false>, dim3(batch_grid(cfg, num_cus)), dim3(64), 0, st, a, batch_level(cfg));
+    hipLaunchKernelGGL(batch_main<false>, dim3(batch_grid(cfg, num_cus)), dim3(64), 0, st, a, batch_level(cfg),
+                       batch_weights(cfg, num_cus));
   return hipGetLastError();
 }
 
@@ -876,7 +967,8 @@ hipError_t make_batch_graph(const TuneBatch& cfg, int num_cus, hipGraph_t* graph
   batch_launch_queries();
   BatchArgs a = batch_args(nullptr, nullptr, 0, nullptr, nullptr, nullptr);
   int level = batch_level(cfg);
-  void* args[] = {&a, &level};
+  uint32_t weights = batch_weights(cfg, num_cus);
+  void* args[] = {&a, &level, &weights};
   const hipKernelNodeParams p = batch_node_params(args, cfg, num_cus);
   *graph = nullptr;
   *exec = nullptr;
@@ -894,7 +986,8 @@ hipError_t set_batch_graph_args(hipGraphExec_t exec, hipGraphNode_t node, const 
                                 int num_cus) {
   BatchArgs a = a0;
   int level = batch_level(cfg);
-  void* args[] = {&a, &level};
+  uint32_t weights = batch_weights(cfg, num_cus);
+  void* args[] = {&a, &level, &weights};
   const hipKernelNodeParams p = batch_node_params(args, cfg, num_cus);
   return hipGraphExecKernelNodeSetParams(exec, node, &p);
 }
