@@ -345,49 +345,11 @@ struct TileBytes {
   __device__ uint32_t operator()(int64_t q) const { return tb[s + (int32_t)q]; }
 };
 
-// The runs of tiles of the waves: logical wave l gets tiles [begin(l), begin(l+1)).  With
-// rank weights w (byte r = weight of dispatch rank r, non-zero) the runs follow the
-// weights of the waves' ranks: the waves of a SIMD are dispatched one after the other,
-// workgroup b being the (4b / grid)-th of its SIMD in a grid of four waves per SIMD, and
-// a SIMD issues from its oldest wave first, so the younger waves are given shorter runs.
-// Logical wave l = x * grid/8 + j (XCD x) holds workgroup 8j + x, of rank j / (grid/32).
-// Without weights the runs are `per` tiles each.
+// The runs of tiles of the waves: logical wave l gets tiles [l * per, (l + 1) * per).
 struct TileRuns {
-  int64_t tiles, per;
-  int grid;
-  uint32_t w;
-  __device__ int64_t weight(int r) const { return (w >> (8 * r)) & 255u; }
-  // Total weight of the waves before logical wave l (the weights of a wave's rank).
-  __device__ int64_t prefix(int64_t l) const {
-    const int64_t q = grid / 32, x = l / (grid / 8), j = l % (grid / 8), r = j / q, rem = j % q;
-    int64_t p = x * q * (weight(0) + weight(1) + weight(2) + weight(3)) + rem * weight((int)r);
-    for (int k = 0; k < (int)r; ++k) p += q * weight(k);
-    return p;
-  }
-  __device__ int64_t total() const { return (int64_t)grid / 4 * (weight(0) + weight(1) + weight(2) + weight(3)); }
-  __device__ int64_t begin(int64_t l) const {
-    if (w == 0) {
-      const int64_t b = l * per;
-      return b < tiles ? b : tiles;
-    }
-    return tiles * prefix(l) / total();  // below 2^31 * 2^20
-  }
-  // The wave whose run holds tile `tile` (< tiles): the last l with begin(l) <= tile, i.e.
-  // the first l with prefix(l) >= ceil((tile + 1) * total / tiles), less one.
-  __device__ int wave_of_tile(int64_t tile) const {
-    if (w == 0) return (int)(tile / per);
-    const int64_t q = grid / 32, sum = weight(0) + weight(1) + weight(2) + weight(3);
-    const int64_t pp = ((tile + 1) * total() + tiles - 1) / tiles - 1;  // first l with prefix(l) > pp
-    const int64_t x = pp / (q * sum), in_x = pp - x * q * sum;
-    int r = 0;
-    int64_t c = 0;  // weight of the ranks before r within the XCD's part
-    while (r < 3 && in_x >= c + q * weight(r)) {
-      c += q * weight(r);
-      ++r;
-    }
-    return (int)(x * (grid / 8) + r * q + (in_x - c) / weight(r));
-  }
-  __device__ int wave_of(int64_t p, int64_t c0) const { return wave_of_tile((p - c0) / kTile); }
+  int64_t tiles;
+  int per;
+  __device__ int wave_of(int64_t p, int64_t c0) const { return (int)((p - c0) / kTile) / per; }
 };
 
 // Cross-wave slot word: arrivals in bits 40..63 and, in bits 0..39, the least partial
@@ -522,7 +484,7 @@ __device__ __forceinline__ void read_tile(const uint8_t* tb, int lane, u32x4 (&x
 // their latency overlaps tile t's checks.  Lane l of a window holds boundary kw + l, the
 // end of string kw + l - 1 and the start of string kw + l.
 template <bool ASCII>
-__global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level, uint32_t rank_weights) {
+__global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
   const DevArgs a = args_of(a0);
   __shared__ __align__(16) uint8_t sbuf[2][kBufBytes];  // tile buffers: the tile at kPad, the 16 bytes before it at 0
   __shared__ uint32_t sflag[64];                         // flagged dwords of the error path: position | flags << 16
@@ -537,13 +499,11 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level, uint32
   // tiles cover [c0, hi]: position hi holds the end check of the last string.  Tile
   // indices are 32-bit (a batch range below 8 TiB), so the loop's comparisons stay scalar.
   const int64_t tiles64 = (hi + 1 - c0 + kTile - 1) / kTile;
-  const TileRuns runs{tiles64, (tiles64 + gridDim.x - 1) / gridDim.x, (int)gridDim.x,
-                      gridDim.x % 32 == 0 ? rank_weights : 0u};
-  const int64_t lw = logical_wave(blockIdx.x, gridDim.x);
-  const int64_t t64 = runs.begin(lw), t_end64 = runs.begin(lw + 1);
-  if (t64 >= t_end64) return;
+  const int64_t per = (tiles64 + gridDim.x - 1) / gridDim.x;
+  const int64_t t64 = logical_wave(blockIdx.x, gridDim.x) * per;
+  if (t64 >= tiles64) return;
   int t = (int)t64;
-  const int t_end = (int)t_end64;
+  const int t_end = (int)(t64 + per < tiles64 ? t64 + per : tiles64);
   // Interior tiles (all bytes inside [lo, hi)) are loaded straight into LDS; the others
   // (the first and last tiles of the range) are read chunk by chunk and masked.
   const int64_t in_first64 = (lo - c0 + kTile - 1) / kTile;
@@ -620,8 +580,7 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level, uint32
   // strings found valid in the previous tile, written during the next one (see step 3)
   int pend_lo = 0, pend_hi = 0;
   int b = 0;  // LDS buffer of tile t
-  const int64_t lo_v = in_vgpr(lo), hi_v = in_vgpr(hi), tiles_v = in_vgpr(tiles64);
-  const uint32_t weights_v = in_vgpr(runs.w);
+  const int64_t lo_v = in_vgpr(lo), hi_v = in_vgpr(hi);
   PriorityLevelsT<int> levels(level != 0, t, t_end - t);
   for (; t < t_end; ++t) {
     levels.step(t);
@@ -847,9 +806,8 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level, uint32
   // the strings that run across waves: the one open at the wave start that ended in it,
   // and the one still open, which runs into the next wave
   if (lane0 && (first_k >= 0 || open_k >= 0)) {
-    const int64_t tiles_u = uniform(tiles_v);
-    const TileRuns runs_u{tiles_u, (tiles_u + gridDim.x - 1) / gridDim.x, (int)gridDim.x,
-                          (uint32_t)__builtin_amdgcn_readfirstlane(weights_v)};
+    const int64_t tiles_u = (uniform(hi_v) + 1 - c0 + kTile - 1) / kTile;
+    const TileRuns runs_u{tiles_u, (int)((tiles_u + gridDim.x - 1) / gridDim.x)};
     CrossWave c1 = cross_wave_begin(first_k, uniform(first_st_v), uniform(first_en_v), uniform(first_d_v), c0, runs_u);
     CrossWave c2 = cross_wave_begin(open_k, uniform(open_st_v), uniform(final_en_v), open_d, c0, runs_u);
     cross_wave_arrive(a, c1, false);
@@ -918,15 +876,6 @@ static int batch_grid(const TuneBatch& cfg, int num_cus) {
   return num_cus * (cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1);
 }
 
-// Rank weights of the tile runs: only for a grid of exactly four resident waves per SIMD,
-// whose waves all start together, the youngest of each SIMD last.
-static uint32_t batch_weights(const TuneBatch& cfg, int num_cus) {
-  return cfg.waves_per_cu == 16 && batch_grid(cfg, num_cus) % 32 == 0 &&
-                 cfg.waves_per_cu <= resident_waves_per_cu(cfg.ascii != 0)
-             ? cfg.rank_weights
-             : 0u;
-}
-
 static int batch_level(const TuneBatch& cfg) {
   return (cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1) <= resident_waves_per_cu(cfg.ascii != 0) ? 1 : 0;
 }
@@ -935,11 +884,9 @@ hipError_t launch_batch(const BatchArgs& a, const TuneBatch& cfg, int num_cus, h
   if (a.n <= 0) return hipSuccess;
   if (a.n > kMaxBatchStrings) return hipErrorInvalidValue;
   if (cfg.ascii)
-    hipLaunchKernelGGL(batch_main<true>, dim3(batch_grid(cfg, num_cus)), dim3(64), 0, st, a, batch_level(cfg),
-                       batch_weights(cfg, num_cus));
+    hipLaunchKernelGGL(batch_main<true>, dim3(batch_grid(cfg, num_cus)), dim3(64), 0, st, a, batch_level(cfg));
   else
-    hipLaunchKernelGGL(batch_main<false>, dim3(batch_grid(cfg, num_cus)), dim3(64), 0, st, a, batch_level(cfg),
-                       batch_weights(cfg, num_cus));
+    hipLaunchKernelGGL(batch_main<false>, dim3(batch_grid(cfg, num_cus)), dim3(64), 0, st, a, batch_level(cfg));
   return hipGetLastError();
 }
 
@@ -967,8 +914,7 @@ hipError_t make_batch_graph(const TuneBatch& cfg, int num_cus, hipGraph_t* graph
   batch_launch_queries();
   BatchArgs a = batch_args(nullptr, nullptr, 0, nullptr, nullptr, nullptr);
   int level = batch_level(cfg);
-  uint32_t weights = batch_weights(cfg, num_cus);
-  void* args[] = {&a, &level, &weights};
+  void* args[] = {&a, &level};
   const hipKernelNodeParams p = batch_node_params(args, cfg, num_cus);
   *graph = nullptr;
   *exec = nullptr;
@@ -986,8 +932,7 @@ hipError_t set_batch_graph_args(hipGraphExec_t exec, hipGraphNode_t node, const 
                                 int num_cus) {
   BatchArgs a = a0;
   int level = batch_level(cfg);
-  uint32_t weights = batch_weights(cfg, num_cus);
-  void* args[] = {&a, &level, &weights};
+  void* args[] = {&a, &level};
   const hipKernelNodeParams p = batch_node_params(args, cfg, num_cus);
   return hipGraphExecKernelNodeSetParams(exec, node, &p);
 }

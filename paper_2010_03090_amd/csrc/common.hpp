@@ -22,7 +22,6 @@ struct TuneSingle {
 struct TuneBatch {
   int waves_per_cu = 16;      // persistent grid: one-wave workgroups per compute unit
   int ascii = 1;              // section 6.4 test of all-ASCII tiles (with its back-off)
-  uint32_t rank_weights = 0;  // run length per dispatch rank of a SIMD's waves (byte r: rank r; 0 = equal runs)
 };
 
 // State word of a single-buffer call: arrivals << kStateShift | least detection
