@@ -176,13 +176,15 @@ def bench_single(u8, lib, synth, torch, dev, stream, sh, args):
     torch.cuda.synchronize()
     log(f"inputs ready in {time.time() - t0:.1f}s: {len(bufs)} x {n} bytes")
 
-    # correctness gate (the oracle checks are in tests/; here the generator's known answers)
-    for name, t, e in zip(names, bufs, expected):
+    # correctness gate (the oracle checks are in tests/; here the generator's known answers,
+    # and for the random bytes the answer before timing, which every timed call must repeat)
+    for i, (name, t, e) in enumerate(zip(names, bufs, expected)):
         got = u8.first_error(t)
         if e is not None and got != e:
             raise SystemExit(f"wrong result on {name}: {got} != {e}")
         if e is None and name != "random" and got != -1:
             raise SystemExit(f"wrong result on {name}: {got} != -1")
+        expected[i] = got
 
     tuned = None if args.no_autotune else autotune_single(u8, lib, bufs[:len(chosen)])
 
