@@ -252,6 +252,21 @@ __device__ __forceinline__ void transpose4(uint32_t a, uint32_t b, uint32_t c, u
   r3 = perm(t3, t2, 0x07060302u);
 }
 
+// The same transposition by another route: rows 0-1 and 2-3 are first gathered from
+// chunks a, c and b, d.  (The comparison form below uses it, so that the compiler keeps
+// the two forms' registers apart instead of holding one transposition for both.)
+__device__ __forceinline__ void transpose4b(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t& r0,
+                                            uint32_t& r1, uint32_t& r2, uint32_t& r3) {
+  const uint32_t x01 = perm(c, a, 0x05040100u);  // a0 a1 c0 c1
+  const uint32_t y01 = perm(d, b, 0x05040100u);  // b0 b1 d0 d1
+  const uint32_t x23 = perm(c, a, 0x07060302u);  // a2 a3 c2 c3
+  const uint32_t y23 = perm(d, b, 0x07060302u);  // b2 b3 d2 d3
+  r0 = perm(y01, x01, 0x06020400u);
+  r1 = perm(y01, x01, 0x07030501u);
+  r2 = perm(y23, x23, 0x06020400u);
+  r3 = perm(y23, x23, 0x07030501u);
+}
+
 // Values of the register before the current one (prev1), and must23's inputs.
 struct LaneCarry {
   uint32_t neg, sh, sl, half;  // of r_{t-1}: sign mask, high-nibble and low-nibble indices, half selector
@@ -292,10 +307,12 @@ __device__ __forceinline__ uint32_t lanes_step(uint32_t acc, uint32_t r, LaneCar
 }
 
 // Errors of the four 16-byte chunks x0..x3 (each preceded by the dword p0..p3), ORed into
-// acc: the same decision as chunk_errors on each chunk.
-template <class V>
+// acc: the same decision as chunk_errors on each chunk.  With PROBE, bit 7 of the bytes of
+// *f_seen is also set where a byte of the chunks is >= 0xF0.
+template <bool PROBE = false, class V>
 __device__ __forceinline__ uint32_t chunks4_errors(uint32_t acc, const V& x0, const V& x1, const V& x2, const V& x3,
-                                                   uint32_t p0, uint32_t p1, uint32_t p2, uint32_t p3) {
+                                                   uint32_t p0, uint32_t p1, uint32_t p2, uint32_t p3,
+                                                   uint32_t* f_seen = nullptr) {
   uint32_t q0, q1, q2, q3;
   transpose4(p0, p1, p2, p3, q0, q1, q2, q3);
   LaneCarry c = lanes_halo(q1, q2, q3);
@@ -306,9 +323,99 @@ __device__ __forceinline__ uint32_t chunks4_errors(uint32_t acc, const V& x0, co
     uint32_t r0, r1, r2, r3;
     transpose4(w[j][0], w[j][1], w[j][2], w[j][3], r0, r1, r2, r3);
     acc = lanes_step(acc, r0, c);
+    if (PROBE) *f_seen |= c.f;
     acc = lanes_step(acc, r1, c);
+    if (PROBE) *f_seen |= c.f;
     acc = lanes_step(acc, r2, c);
+    if (PROBE) *f_seen |= c.f;
     acc = lanes_step(acc, r3, c);
+    if (PROBE) *f_seen |= c.f;
+  }
+  return acc;
+}
+
+// ---- text without bytes >= 0xF0, across the byte lanes ---------------------------------------
+// Where no byte of a position's window (its byte c and the three before it, p1 p2 p3) is
+// >= 0xF0, must23 (6.2) is M = p2 >= 0xE0 and the table product of 6.1 is non-zero for: a
+// lead p1 before a byte that is not a continuation (too short), an ASCII p1 before a
+// continuation (too long), a continuation after C0 or C1 (overlong 2), after E0 below A0
+// (overlong 3) and after ED from A0 on (surrogate); bit 7 is two continuations in a row.
+// With K = "c is a continuation", the checks of 6.1-6.2 then flag a position iff
+//   K = 0:  p1 >= 0xC0, or M;
+//   K = 1:  p1 < 0x80, or (p1 >= 0xC0) == M, or p1 is C0/C1, or p1 is ED and c >= A0, or
+//           p1 is E0 and c < A0
+// (a continuation p1 is flagged iff not M; a lead p1 iff M or a special case).  Every
+// comparison is bit 7 of v_lerp_u8, so a position costs eight comparisons and eight
+// three-input logic operations, against the nineteen operations of the table form.
+//
+// To know that no byte >= 0xF0 was there, a byte >= 0xF0 as p1 flags the position after
+// it (it joins the C0/C1 case), and the two bytes before a run are tested on their own.
+// A run that comes out without any flag therefore had no such byte in any window and
+// no error; otherwise the caller checks it again with the table form.
+
+struct ThreeCarry {
+  uint32_t a1;    // r_{t-1} itself (bit 7: >= 0x80)
+  uint32_t l1;    // r_{t-1} >= 0xC0
+  uint32_t e1;    // r_{t-1} >= 0xE0 (M two positions on)
+  uint32_t m;     // r_{t-2} >= 0xE0: M of this position
+  uint32_t u, v;  // r_{t-1} is C0, C1 or >= 0xF0, or (u) ED, or (v) E0
+};
+
+__device__ __forceinline__ void three_lead(uint32_t r, uint32_t l, uint32_t e, uint32_t& u, uint32_t& v) {
+  const uint32_t p = UTF8V_BITOP3(l, ge_mask7(r, 0x3E3E3E3Eu), ge_mask7(r, 0x10101010u), (a & ~b) | c);
+  u = UTF8V_BITOP3(p, ge_mask7(r, 0x13131313u), ge_mask7(r, 0x12121212u), a | (b & ~c));  // ... or ED
+  v = UTF8V_BITOP3(p, e, ge_mask7(r, 0x1F1F1F1Fu), a | (b & ~c));                          // ... or E0
+}
+
+// Carried values for a run after the registers q1, q2, q3 (bytes t-3, t-2, t-1); a byte
+// >= 0xF0 in q1 or q2 is flagged in acc.
+__device__ __forceinline__ ThreeCarry three_halo(uint32_t q1, uint32_t q2, uint32_t q3, uint32_t& acc) {
+  ThreeCarry c;
+  c.a1 = q3;
+  c.l1 = ge_mask7(q3, 0x40404040u);
+  c.e1 = ge_mask7(q3, 0x20202020u);
+  c.m = ge_mask7(q2, 0x20202020u);
+  three_lead(q3, c.l1, c.e1, c.u, c.v);
+  acc = UTF8V_BITOP3(acc, ge_mask7(q1, 0x10101010u), ge_mask7(q2, 0x10101010u), a | b | c);
+  return c;
+}
+
+// Flags of register r (bit 7 of each byte) ORed into acc; c moves on to r.
+__device__ __forceinline__ uint32_t three_step(uint32_t acc, uint32_t r, ThreeCarry& c) {
+  const uint32_t l = ge_mask7(r, 0x40404040u);
+  const uint32_t e = ge_mask7(r, 0x20202020u);
+  const uint32_t k = UTF8V_BITOP3(r, l, 0u, a & ~b);  // continuation
+  const uint32_t w = UTF8V_BITOP3(k, c.l1, c.m, (a & ~(b ^ c)) | (~a & (b | c)));
+  const uint32_t s = select_bits(ge_mask7(r, 0x60606060u), c.u, c.v);  // c >= A0 ? (.., ED) : (.., E0)
+  const uint32_t y = UTF8V_BITOP3(w, k, c.a1, a | (b & ~c));       // ... or an ASCII p1 before a continuation
+  acc = UTF8V_BITOP3(acc, y, s, a | b | c);
+  c.m = c.e1;
+  c.e1 = e;
+  c.l1 = l;
+  c.a1 = r;
+  three_lead(r, l, e, c.u, c.v);
+  return acc;
+}
+
+// The four 16-byte chunks x0..x3 (each preceded by the dword p0..p3) in the form above:
+// bit 7 of a byte of the result is set where a position is flagged or a byte >= 0xF0
+// was seen (other bits are left over from the comparisons).
+template <class V>
+__device__ __forceinline__ uint32_t chunks4_three(uint32_t acc, const V& x0, const V& x1, const V& x2, const V& x3,
+                                                  uint32_t p0, uint32_t p1, uint32_t p2, uint32_t p3) {
+  uint32_t q0, q1, q2, q3;
+  transpose4b(p0, p1, p2, p3, q0, q1, q2, q3);
+  ThreeCarry c = three_halo(q1, q2, q3, acc);
+  const uint32_t w[4][4] = {{x0.x, x1.x, x2.x, x3.x}, {x0.y, x1.y, x2.y, x3.y},
+                            {x0.z, x1.z, x2.z, x3.z}, {x0.w, x1.w, x2.w, x3.w}};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    uint32_t r0, r1, r2, r3;
+    transpose4b(w[j][0], w[j][1], w[j][2], w[j][3], r0, r1, r2, r3);
+    acc = three_step(acc, r0, c);
+    acc = three_step(acc, r1, c);
+    acc = three_step(acc, r2, c);
+    acc = three_step(acc, r3, c);
   }
   return acc;
 }

@@ -101,12 +101,19 @@ __device__ __forceinline__ void store_tile(const u32x4 (&x)[U], uint8_t* __restr
   }
 }
 
+// Whether a wave tries the comparison form for text without bytes >= 0xF0 (see
+// single_tile), and the back-off of its looks for such bytes while it does not.
+struct ThreeTrials {
+  bool on = false;
+  AsciiBackoff probe;
+};
+
 // Validate one wave tile already in registers.  `carry` (lane 0) holds the dword
 // before the tile and leaves with the tile's last dword.
 template <int U, bool ASCII, bool FULL>
 __device__ __forceinline__ void single_tile(const u32x4 (&x)[U], uint64_t base, uint64_t i1, int lane,
                                             uint32_t& carry, uint64_t& dmin, AsciiBackoff& ascii,
-                                            AsciiBackoff& two) {
+                                            AsciiBackoff& two, ThreeTrials& three) {
   // previous dword of each chunk: lane l-1's last dword (lane 0: lane 63 of the previous slab)
   uint32_t prev[U];
   const bool lane0 = lane == 0;
@@ -148,10 +155,35 @@ __device__ __forceinline__ void single_tile(const u32x4 (&x)[U], uint64_t base, 
       }
       acc &= 0x80808080u;
     } else {
+      // Text of characters of at most three bytes: while the tiles before had no byte >=
+      // 0xF0, a tile is first tried in the comparison form; when that flags anything (an
+      // error, or a byte >= 0xF0 that the form does not cover) the tile is checked again
+      // with the tables.  The table form then also looks for bytes >= 0xF0, and so it does
+      // now and then (with the back-off) while trials are off; finding none turns them on.
+      bool clean = false;
+      if (three.on) {
+        uint32_t f = 0;
 #pragma unroll
-      for (int u = 0; u < U; u += 4)
-        acc = chunks4_errors(acc, x[u], x[u + 1], x[u + 2], x[u + 3], prev[u], prev[u + 1], prev[u + 2],
-                             prev[u + 3]);
+        for (int u = 0; u < U; u += 4)
+          f = chunks4_three(f, x[u], x[u + 1], x[u + 2], x[u + 3], prev[u], prev[u + 1], prev[u + 2], prev[u + 3]);
+        clean = __all((f & 0x80808080u) == 0);
+      }
+      if (!clean) {
+        if (three.on || three.probe.due()) {
+          uint32_t f_seen = 0;
+#pragma unroll
+          for (int u = 0; u < U; u += 4)
+            acc = chunks4_errors<true>(acc, x[u], x[u + 1], x[u + 2], x[u + 3], prev[u], prev[u + 1], prev[u + 2],
+                                       prev[u + 3], &f_seen);
+          three.on = __all((f_seen & 0x80808080u) == 0);
+          three.probe.result(three.on);
+        } else {
+#pragma unroll
+          for (int u = 0; u < U; u += 4)
+            acc = chunks4_errors(acc, x[u], x[u + 1], x[u + 2], x[u + 3], prev[u], prev[u + 1], prev[u + 2],
+                                 prev[u + 3]);
+        }
+      }
     }
   } else {
 #pragma unroll
@@ -287,6 +319,7 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
   uint64_t dmin = kNone;
   if (t < t_end) {
     AsciiBackoff ascii, two;
+    ThreeTrials three;
     uint32_t carry = prev_dword(a, a.i0 + t * W);
     // the buffer's last tile may be partial
     const uint64_t t_full = (t_end == a.tiles && a.i0 + a.tiles * W > a.i1) ? t_end - 1 : t_end;
@@ -299,14 +332,14 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
         levels.step(t);
         load_tile<U, true>(xb, a.buf, a.i0 + (t + 1) * W, a.i1, lane);
         if (COPY) store_tile<U, true>(xa, a.dst, a.i0 + t * W, a.i1, lane);
-        single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii, two);
+        single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii, two, three);
         if (t + 2 < t_full) load_tile<U, true>(xa, a.buf, a.i0 + (t + 2) * W, a.i1, lane);
         if (COPY) store_tile<U, true>(xb, a.dst, a.i0 + (t + 1) * W, a.i1, lane);
-        single_tile<U, ASCII, true>(xb, a.i0 + (t + 1) * W, a.i1, lane, carry, dmin, ascii, two);
+        single_tile<U, ASCII, true>(xb, a.i0 + (t + 1) * W, a.i1, lane, carry, dmin, ascii, two, three);
       }
       if (t < t_full) {
         if (COPY) store_tile<U, true>(xa, a.dst, a.i0 + t * W, a.i1, lane);
-        single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii, two);
+        single_tile<U, ASCII, true>(xa, a.i0 + t * W, a.i1, lane, carry, dmin, ascii, two, three);
         ++t;
       }
     }
@@ -314,7 +347,7 @@ __global__ __launch_bounds__(256) void single_main(SingleArgs a) {
       u32x4 x[U];
       load_tile<U, false>(x, a.buf, a.i0 + t * W, a.i1, lane);
       if (COPY) store_tile<U, false>(x, a.dst, a.i0 + t * W, a.i1, lane);
-      single_tile<U, ASCII, false>(x, a.i0 + t * W, a.i1, lane, carry, dmin, ascii, two);
+      single_tile<U, ASCII, false>(x, a.i0 + t * W, a.i1, lane, carry, dmin, ascii, two, three);
     }
   }
   dmin = edge < dmin ? edge : dmin;

@@ -98,7 +98,7 @@ def test_single_error_at_every_offset_and_alignment(u8):
     positions = sorted(set(list(range(0, 80)) + [k + d for k in (1024, 2048, 3072, 4096, 8192 - 16)
                                                  for d in range(-6, 7)] + list(rng.integers(0, base_len, 200))))
     checked = 0
-    for variant in ("mixed", "latin", "ascii", "emoji"):
+    for variant in ("mixed", "latin", "ascii", "emoji", "cjk"):
         clean = synth.text(base_len, variant, 7)
         for pos in positions:
             for cls in range(7):
@@ -150,6 +150,45 @@ def test_two_byte_text_with_longer_characters_at_chunk_edges(u8):
                 valid += exp == -1
     assert valid > 20
     say(f"checked {len(edges) * sum(c.size for c in chars) * 2} buffers, {valid} valid")
+
+
+def test_three_byte_text_with_other_characters_at_chunk_edges(u8):
+    """Text of characters of at most three bytes first takes a comparison form of the
+    checks per tile; a byte >= 0xF0 in a chunk or in the three bytes before it, or an
+    error, must send the tile to the table form.  4-byte characters (valid, cut short, too
+    large, overlong), bytes F5..FF and the 3-byte special cases are placed across each
+    chunk, slab and tile edge of CJK-like text, at every split, at two alignments and
+    with the section 6.4 test on and off."""
+    n = 40 * 1024
+    base = np.tile(np.array([0xE4, 0xB8, 0xAD, 0xE6, 0x96, 0x87, 0x41], np.uint8), n // 7 + 1)[:n]
+    base[-(n % 7 or 7):] = 0x41
+    edges = [16 * k for k in range(1, 6)] + [1024, 2048, 3072, 4096, 8192, 12288, 20480 + 16]
+    chars = [np.array(c, np.uint8) for c in ((0xF0, 0x9F, 0x98, 0x80), (0xF4, 0x8F, 0xBF, 0xBF), (0xF0, 0x9F, 0x98),
+                                             (0xF4, 0x90, 0x80, 0x80), (0xF0, 0x80, 0x80, 0x80), (0xF5, 0x80, 0x80),
+                                             (0xFF,), (0xED, 0xA0, 0x80), (0xE0, 0x80, 0x80), (0xE0, 0xA0, 0x80),
+                                             (0xED, 0x9F, 0xBF), (0xC0, 0x80), (0x80,), (0xE4, 0xB8))]
+    big = dev(np.zeros(n + 16, np.uint8))
+    old = u8.get_config()
+    valid = checked = 0
+    try:
+        for ascii_ in (0, 1):
+            u8.set_config(ascii=ascii_)
+            for e in edges:
+                for ch in chars:
+                    for k in range(1, ch.size + 1):
+                        buf = base.copy()
+                        buf[e - k: e - k + ch.size] = ch
+                        exp = oracle.first_error(buf)
+                        for shift in (0, 5):
+                            big[shift: shift + n].copy_(torch.from_numpy(buf))
+                            got = u8.first_error(big[shift: shift + n])
+                            assert got == exp, (ascii_, e, ch.tolist(), k, shift, got, exp)
+                            checked += 1
+                        valid += exp == -1
+    finally:
+        u8.set_config(**old)
+    assert valid > 20
+    say(f"checked {checked} buffers, {valid // 2} valid")
 
 
 def test_sizes_and_alignments_valid_and_random(u8):

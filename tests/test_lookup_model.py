@@ -175,3 +175,79 @@ def test_short_form_for_text_without_bytes_from_e0():
             window = np.stack([np.full_like(p, b3), np.full_like(p, b2), p, c], axis=1)
             full = lm.position_errors(window)[:, 3] != 0
             assert np.array_equal(full, short), (hex(b3), hex(b2))
+
+
+# ---- the comparison form for text without bytes >= 0xF0 ---------------------------------------
+# A restatement of the GPU kernels' comparison form (lookup.hpp, three_halo / three_step), with
+# each comparison taken, as on the GPU, from bit 7 of the byte average (v + k) >> 1.
+
+def _ge(v, k):
+    """bit 7 of v_lerp_u8(v, k): v >= 256 - k."""
+    return ((v.astype(np.uint16) + k) >> 1 & 0x80) != 0
+
+
+def _three_lead(r):
+    """(u, v) of byte r as the byte before: C0, C1 or >= F0, or (u) ED, or (v) E0."""
+    p = (_ge(r, 0x40) & ~_ge(r, 0x3E)) | _ge(r, 0x10)
+    return p | (_ge(r, 0x13) & ~_ge(r, 0x12)), p | (_ge(r, 0x20) & ~_ge(r, 0x1F))
+
+
+def _three_flags(run):
+    """Flags of positions 3.. of each row of `run` (the first three columns are the bytes
+    before the run) and the flag of the two-byte test on the first two columns."""
+    run = np.asarray(run, np.uint8)
+    q1, q2, q3 = run[:, 0], run[:, 1], run[:, 2]
+    halo = _ge(q1, 0x10) | _ge(q2, 0x10)
+    a1, l1, e1, m = q3 >= 0x80, _ge(q3, 0x40), _ge(q3, 0x20), _ge(q2, 0x20)
+    u, v = _three_lead(q3)
+    out = []
+    for t in range(3, run.shape[1]):
+        r = run[:, t]
+        l, e = _ge(r, 0x40), _ge(r, 0x20)
+        k = (r >= 0x80) & ~l
+        w = (k & ~(l1 ^ m)) | (~k & (l1 | m))
+        s = np.where(_ge(r, 0x60), u, v)
+        out.append(w | (k & ~a1) | s)
+        m, e1, l1, a1 = e1, e, l, r >= 0x80
+        u, v = _three_lead(r)
+    return np.stack(out, 1), halo
+
+
+def test_three_byte_form_for_text_without_bytes_from_f0():
+    """Where a position and the three bytes before it are all below 0xF0, the comparison form
+    flags exactly the positions the lookup checks (6.1-6.2) flag: every (byte two before,
+    byte before, byte) triple below 0xF0, with the byte three before at 0x00 and at 0xEF
+    (below 0xF0 it cannot matter: must23 then only reads the byte two before)."""
+    p1, c = np.meshgrid(np.arange(0xF0, dtype=np.uint8), np.arange(0xF0, dtype=np.uint8), indexing="ij")
+    p1, c = p1.reshape(-1), c.reshape(-1)
+    for b3 in (0x00, 0xEF):
+        for b2 in range(0xF0):
+            run = np.stack([np.full_like(p1, 0), np.full_like(p1, b3), np.full_like(p1, b2), p1, c], axis=1)
+            model = lm.position_errors(run)[:, 4] != 0
+            flags, halo = _three_flags(run)
+            assert not halo.any()
+            assert np.array_equal(flags[:, 1], model), (hex(b3), hex(b2))
+
+
+def test_three_byte_form_flags_every_run_with_a_byte_from_f0():
+    """A run that the comparison form leaves without a flag holds no byte >= 0xF0 in its
+    three bytes before or before its last byte, and then agrees with the lookup checks at
+    every position; a run with such a byte gets a flag.  Random runs of 8 bytes (and the
+    3 before) over an alphabet with a member of every byte class."""
+    alpha = np.array([0x00, 0x41, 0x7F, 0x80, 0x8F, 0x90, 0x9F, 0xA0, 0xBF, 0xC0, 0xC1, 0xC2, 0xDF, 0xE0, 0xE1,
+                      0xEC, 0xED, 0xEE, 0xEF, 0xF0, 0xF1, 0xF4, 0xF5, 0xFF], np.uint8)
+    rng = np.random.default_rng(5)
+    for _ in range(4):
+        run = alpha[rng.integers(0, alpha.size, (500_000, 11))]
+        # runs of mostly continuation bytes and three-byte leads, as in CJK text
+        cjk = np.array([0x41, 0x80, 0x9F, 0xA0, 0xBF, 0xE0, 0xE4, 0xED, 0xEF, 0xF0, 0xF4, 0xF5], np.uint8)
+        run = np.concatenate([run, cjk[rng.integers(0, cjk.size, (500_000, 11))]])
+        flags, halo = _three_flags(run)
+        flagged = flags.any(axis=1) | halo
+        has_f0 = (run[:, :-1] >= 0xF0).any(axis=1)
+        model = lm.position_errors(run)[:, 3:11] != 0
+        assert flagged[has_f0].all()
+        clean = ~has_f0
+        assert np.array_equal(flags[clean], model[clean])
+        # the form flags no more than the lookup checks do where it applies
+        assert (flagged[clean] == model[clean].any(axis=1)).all()
