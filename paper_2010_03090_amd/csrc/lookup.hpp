@@ -289,9 +289,25 @@ __device__ __forceinline__ LaneCarry lanes_halo(uint32_t q1, uint32_t q2, uint32
   return c;
 }
 
-// Errors of register r (sections 6.1-6.2), ORed into acc; c moves on to r.
-__device__ __forceinline__ uint32_t lanes_step(uint32_t acc, uint32_t r, LaneCarry& c) {
-  const uint32_t neg = sign_mask(r);
+// 4x4 byte transpose (as transpose4) that also gives the sign masks of rows 0 and 2: the
+// first step gathers each pair of rows with row 0 (2) in the odd bytes, where
+// v_perm_b32's sign selectors read it.
+__device__ __forceinline__ void transpose4s(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t& r0,
+                                            uint32_t& r1, uint32_t& r2, uint32_t& r3, uint32_t& n0, uint32_t& n2) {
+  const uint32_t x10 = perm(c, a, 0x04050001u);  // a1 a0 c1 c0
+  const uint32_t y10 = perm(d, b, 0x04050001u);  // b1 b0 d1 d0
+  const uint32_t x32 = perm(c, a, 0x06070203u);  // a3 a2 c3 c2
+  const uint32_t y32 = perm(d, b, 0x06070203u);  // b3 b2 d3 d2
+  r0 = perm(y10, x10, 0x07030501u);
+  r1 = perm(y10, x10, 0x06020400u);
+  r2 = perm(y32, x32, 0x07030501u);
+  r3 = perm(y32, x32, 0x06020400u);
+  n0 = perm(y10, x10, kSignSel);
+  n2 = perm(y32, x32, kSignSel);
+}
+
+// Errors of register r (sections 6.1-6.2) with sign mask neg, ORed into acc; c moves on to r.
+__device__ __forceinline__ uint32_t lanes_step(uint32_t acc, uint32_t r, uint32_t neg, LaneCarry& c) {
   const uint32_t sh = (r >> 4) & 0x07070707u;
   const uint32_t sc = lookup3(c.sh, c.sl, sh, c.neg, neg, c.half);
   const uint32_t g = or_and(ge_mask7(r, 0x20202020u), c.f, 0x80808080u);
@@ -320,15 +336,15 @@ __device__ __forceinline__ uint32_t chunks4_errors(uint32_t acc, const V& x0, co
                             {x0.z, x1.z, x2.z, x3.z}, {x0.w, x1.w, x2.w, x3.w}};
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    uint32_t r0, r1, r2, r3;
-    transpose4(w[j][0], w[j][1], w[j][2], w[j][3], r0, r1, r2, r3);
-    acc = lanes_step(acc, r0, c);
+    uint32_t r0, r1, r2, r3, n0, n2;
+    transpose4s(w[j][0], w[j][1], w[j][2], w[j][3], r0, r1, r2, r3, n0, n2);
+    acc = lanes_step(acc, r0, n0, c);
     if (PROBE) *f_seen |= c.f;
-    acc = lanes_step(acc, r1, c);
+    acc = lanes_step(acc, r1, sign_mask(r1), c);
     if (PROBE) *f_seen |= c.f;
-    acc = lanes_step(acc, r2, c);
+    acc = lanes_step(acc, r2, n2, c);
     if (PROBE) *f_seen |= c.f;
-    acc = lanes_step(acc, r3, c);
+    acc = lanes_step(acc, r3, sign_mask(r3), c);
     if (PROBE) *f_seen |= c.f;
   }
   return acc;
