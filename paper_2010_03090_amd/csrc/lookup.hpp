@@ -356,21 +356,24 @@ __device__ __forceinline__ uint32_t chunks4_errors(uint32_t acc, const V& x0, co
 // lead p1 before a byte that is not a continuation (too short), an ASCII p1 before a
 // continuation (too long), a continuation after C0 or C1 (overlong 2), after E0 below A0
 // (overlong 3) and after ED from A0 on (surrogate); bit 7 is two continuations in a row.
-// With K = "c is a continuation", the checks of 6.1-6.2 then flag a position iff
-//   K = 0:  p1 >= 0xC0, or M;
-//   K = 1:  p1 < 0x80, or (p1 >= 0xC0) == M, or p1 is C0/C1, or p1 is ED and c >= A0, or
-//           p1 is E0 and c < A0
-// (a continuation p1 is flagged iff not M; a lead p1 iff M or a special case).  Every
-// comparison is bit 7 of v_lerp_u8, so a position costs eight comparisons and eight
-// three-input logic operations, against the nineteen operations of the table form.
+// With K = "c is a continuation" and N = "p1 >= 0xC0, or M" (c must be a continuation),
+// this form flags a position iff
+//   K != N, or K and (p1 is C0/C1, or p1 is ED and c >= A0, or p1 is E0 and c < A0).
+// The checks of 6.1-6.2 flag exactly these positions and, besides, a continuation after an
+// ASCII or lead p1 where M holds; there the position before is flagged by both (p1 is not
+// a continuation, and the byte before it is a lead >= 0xE0), so the first flagged position
+// of any text is the same.  Every comparison is bit 7 of v_lerp_u8: a position costs eight
+// comparisons and seven three-input logic operations, against nineteen operations in the
+// table form.
 //
 // To know that no byte >= 0xF0 was there, a byte >= 0xF0 as p1 flags the position after
 // it (it joins the C0/C1 case), and the two bytes before a run are tested on their own.
-// A run that comes out without any flag therefore had no such byte in any window and
-// no error; otherwise the caller checks it again with the table form.
+// A run that comes out without any flag therefore had no such byte in any window and no
+// first flag of the checks (a flag of theirs that this form leaves out follows a flag of
+// both, at the last byte of the run before at the latest); otherwise the caller checks it
+// again with the table form.
 
 struct ThreeCarry {
-  uint32_t a1;    // r_{t-1} itself (bit 7: >= 0x80)
   uint32_t l1;    // r_{t-1} >= 0xC0
   uint32_t e1;    // r_{t-1} >= 0xE0 (M two positions on)
   uint32_t m;     // r_{t-2} >= 0xE0: M of this position
@@ -387,7 +390,6 @@ __device__ __forceinline__ void three_lead(uint32_t r, uint32_t l, uint32_t e, u
 // >= 0xF0 in q1 or q2 is flagged in acc.
 __device__ __forceinline__ ThreeCarry three_halo(uint32_t q1, uint32_t q2, uint32_t q3, uint32_t& acc) {
   ThreeCarry c;
-  c.a1 = q3;
   c.l1 = ge_mask7(q3, 0x40404040u);
   c.e1 = ge_mask7(q3, 0x20202020u);
   c.m = ge_mask7(q2, 0x20202020u);
@@ -400,15 +402,13 @@ __device__ __forceinline__ ThreeCarry three_halo(uint32_t q1, uint32_t q2, uint3
 __device__ __forceinline__ uint32_t three_step(uint32_t acc, uint32_t r, ThreeCarry& c) {
   const uint32_t l = ge_mask7(r, 0x40404040u);
   const uint32_t e = ge_mask7(r, 0x20202020u);
-  const uint32_t k = UTF8V_BITOP3(r, l, 0u, a & ~b);  // continuation
-  const uint32_t w = UTF8V_BITOP3(k, c.l1, c.m, (a & ~(b ^ c)) | (~a & (b | c)));
+  const uint32_t k = UTF8V_BITOP3(r, l, 0u, a & ~b);                   // continuation
+  const uint32_t x = UTF8V_BITOP3(c.l1, c.m, k, (a | b) ^ c);          // K != N
   const uint32_t s = select_bits(ge_mask7(r, 0x60606060u), c.u, c.v);  // c >= A0 ? (.., ED) : (.., E0)
-  const uint32_t y = UTF8V_BITOP3(w, k, c.a1, a | (b & ~c));       // ... or an ASCII p1 before a continuation
-  acc = UTF8V_BITOP3(acc, y, s, a | b | c);
+  acc = UTF8V_BITOP3(acc, x, s, a | b | c);
   c.m = c.e1;
   c.e1 = e;
   c.l1 = l;
-  c.a1 = r;
   three_lead(r, l, e, c.u, c.v);
   return acc;
 }

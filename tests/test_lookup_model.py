@@ -198,56 +198,62 @@ def _three_flags(run):
     run = np.asarray(run, np.uint8)
     q1, q2, q3 = run[:, 0], run[:, 1], run[:, 2]
     halo = _ge(q1, 0x10) | _ge(q2, 0x10)
-    a1, l1, e1, m = q3 >= 0x80, _ge(q3, 0x40), _ge(q3, 0x20), _ge(q2, 0x20)
+    l1, e1, m = _ge(q3, 0x40), _ge(q3, 0x20), _ge(q2, 0x20)
     u, v = _three_lead(q3)
     out = []
     for t in range(3, run.shape[1]):
         r = run[:, t]
         l, e = _ge(r, 0x40), _ge(r, 0x20)
         k = (r >= 0x80) & ~l
-        w = (k & ~(l1 ^ m)) | (~k & (l1 | m))
-        s = np.where(_ge(r, 0x60), u, v)
-        out.append(w | (k & ~a1) | s)
-        m, e1, l1, a1 = e1, e, l, r >= 0x80
+        out.append(((l1 | m) ^ k) | np.where(_ge(r, 0x60), u, v))
+        m, e1, l1 = e1, e, l
         u, v = _three_lead(r)
     return np.stack(out, 1), halo
 
 
 def test_three_byte_form_for_text_without_bytes_from_f0():
     """Where a position and the three bytes before it are all below 0xF0, the comparison form
-    flags exactly the positions the lookup checks (6.1-6.2) flag: every (byte two before,
-    byte before, byte) triple below 0xF0, with the byte three before at 0x00 and at 0xEF
-    (below 0xF0 it cannot matter: must23 then only reads the byte two before)."""
+    flags a subset of what the lookup checks (6.1-6.2) flag, and where it leaves a flag of
+    theirs out it flags the position before (so every text keeps its first flagged
+    position): every (byte two before, byte before, byte) triple below 0xF0, with the byte
+    three before at 0x00 and at 0xEF (below 0xF0 it cannot change the checks at the byte)."""
     p1, c = np.meshgrid(np.arange(0xF0, dtype=np.uint8), np.arange(0xF0, dtype=np.uint8), indexing="ij")
     p1, c = p1.reshape(-1), c.reshape(-1)
+    left_out = 0
     for b3 in (0x00, 0xEF):
         for b2 in range(0xF0):
             run = np.stack([np.full_like(p1, 0), np.full_like(p1, b3), np.full_like(p1, b2), p1, c], axis=1)
-            model = lm.position_errors(run)[:, 4] != 0
+            model = lm.position_errors(run)[:, 3:5] != 0
             flags, halo = _three_flags(run)
             assert not halo.any()
-            assert np.array_equal(flags[:, 1], model), (hex(b3), hex(b2))
+            assert not (flags & ~model).any(), (hex(b3), hex(b2))
+            out = model[:, 1] & ~flags[:, 1]
+            assert flags[out, 0].all(), (hex(b3), hex(b2))
+            left_out += int(out.sum())
+    assert left_out > 0  # the case exists: it is the one the form leaves to the position before
 
 
-def test_three_byte_form_flags_every_run_with_a_byte_from_f0():
-    """A run that the comparison form leaves without a flag holds no byte >= 0xF0 in its
-    three bytes before or before its last byte, and then agrees with the lookup checks at
-    every position; a run with such a byte gets a flag.  Random runs of 8 bytes (and the
-    3 before) over an alphabet with a member of every byte class."""
+def test_three_byte_form_keeps_the_first_flag_and_flags_bytes_from_f0():
+    """Whole texts (zeros before them) without a byte >= 0xF0 before their last byte get
+    their first flag from the comparison form where the lookup checks put it, and no flag
+    the checks do not have; a run taken from the middle of a text with a byte >= 0xF0 in
+    its three bytes before or before its last byte gets a flag.  Random 11-byte texts over
+    an alphabet with a member of every byte class, and over CJK-like bytes."""
     alpha = np.array([0x00, 0x41, 0x7F, 0x80, 0x8F, 0x90, 0x9F, 0xA0, 0xBF, 0xC0, 0xC1, 0xC2, 0xDF, 0xE0, 0xE1,
                       0xEC, 0xED, 0xEE, 0xEF, 0xF0, 0xF1, 0xF4, 0xF5, 0xFF], np.uint8)
+    cjk = np.array([0x41, 0x80, 0x9F, 0xA0, 0xBF, 0xE0, 0xE4, 0xED, 0xEF, 0xF0, 0xF4, 0xF5], np.uint8)
     rng = np.random.default_rng(5)
     for _ in range(4):
-        run = alpha[rng.integers(0, alpha.size, (500_000, 11))]
-        # runs of mostly continuation bytes and three-byte leads, as in CJK text
-        cjk = np.array([0x41, 0x80, 0x9F, 0xA0, 0xBF, 0xE0, 0xE4, 0xED, 0xEF, 0xF0, 0xF4, 0xF5], np.uint8)
-        run = np.concatenate([run, cjk[rng.integers(0, cjk.size, (500_000, 11))]])
-        flags, halo = _three_flags(run)
-        flagged = flags.any(axis=1) | halo
-        has_f0 = (run[:, :-1] >= 0xF0).any(axis=1)
-        model = lm.position_errors(run)[:, 3:11] != 0
-        assert flagged[has_f0].all()
-        clean = ~has_f0
-        assert np.array_equal(flags[clean], model[clean])
-        # the form flags no more than the lookup checks do where it applies
-        assert (flagged[clean] == model[clean].any(axis=1)).all()
+        text = np.concatenate([alpha[rng.integers(0, alpha.size, (500_000, 11))],
+                               cjk[rng.integers(0, cjk.size, (500_000, 11))]])
+        # a whole text: zeros before it
+        flags, _ = _three_flags(np.concatenate([np.zeros((text.shape[0], 3), np.uint8), text], 1))
+        model = lm.position_errors(text)[:, :11] != 0
+        clean = ~(text[:, :-1] >= 0xF0).any(axis=1)
+        assert not (flags[clean] & ~model[clean]).any()
+        first = lambda f: np.where(f.any(axis=1), f.argmax(axis=1), -1)
+        assert np.array_equal(first(flags[clean]), first(model[clean]))
+        # a run from the middle of a text: its first three bytes are the bytes before it
+        flags, halo = _three_flags(text)
+        has_f0 = (text[:, :-1] >= 0xF0).any(axis=1)
+        assert (flags.any(axis=1) | halo)[has_f0].all()
