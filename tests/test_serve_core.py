@@ -6,6 +6,8 @@ over random reserve / release sequences; the layout against its invariants.
 """
 import ctypes
 import os
+import platform
+import shutil
 import subprocess
 
 import numpy as np
@@ -125,8 +127,18 @@ def test_scheduler_under_thread_sanitizer(tmp_path):
     exe = str(tmp_path / "serve_sched_check")
     subprocess.check_call(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=thread", "-pthread", "-o", exe,
                            os.path.join(HERE, "serve_sched_check.cpp")])
-    r = subprocess.run([exe], capture_output=True, text=True, timeout=120,
-                       env={**os.environ, "TSAN_OPTIONS": "halt_on_error=1"})
-    assert r.returncode == 0, r.stderr[-3000:]
-    assert "ThreadSanitizer" not in r.stderr, r.stderr[-3000:]
-    assert "scheduler ok" in r.stdout
+    # ThreadSanitizer's shadow memory can collide with a randomized mapping at start-up
+    # ("FATAL: ThreadSanitizer: unexpected memory mapping"), which says nothing about the
+    # code under test: run with address randomization off where setarch exists, and start
+    # once more after such a start-up failure (never after a race report or a failed check)
+    cmd = (["setarch", platform.machine(), "-R", exe] if shutil.which("setarch") else [exe])
+    for _ in range(2):
+        r = subprocess.run(cmd, capture_output=True, text=True, timeout=120,
+                           env={**os.environ, "TSAN_OPTIONS": "halt_on_error=1"})
+        if not ("FATAL: ThreadSanitizer" in r.stderr and "check failed" not in r.stderr
+                and "WARNING: ThreadSanitizer" not in r.stderr):
+            break
+    report = f"rc={r.returncode}\nstdout:\n{r.stdout[-2000:]}\nstderr:\n{r.stderr[-3000:]}"
+    assert r.returncode == 0, report
+    assert "ThreadSanitizer" not in r.stderr, report
+    assert "scheduler ok" in r.stdout, report
