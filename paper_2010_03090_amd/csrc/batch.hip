@@ -594,12 +594,18 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
     if (edge_cur) edge_tile(data, ts, lo_v, hi_v, buf, lane);
     // 2. boundaries of the window [ts-4, te): [k0, k1), those in [ts, te): [kb, k1).  Lane l
     // holds boundary k0 + l, as a 32-bit position relative to ts.  A tile inside one string
-    // (the window's first boundary lies past it) has none; a tile with 64 or more is dense:
-    // its windows after the first are read in the error path.
-    const int32_t rv = tile_rel(v, ts);
-    const int cnt = __popcll(__ballot(rv < kTile));
-    const int cnt_next = __popcll(__ballot(rv < kTile - 4));
-    const int cnt_before = __popcll(__ballot(rv < 0));
+    // (the window's first boundary, lane 0's, lies past it) has none, and skips this and
+    // the bookkeeping of steps 5-6; a tile with 64 or more is dense: its windows after the
+    // first are read in the error path.
+    const bool spans = uniform(v) >= te;
+    int32_t rv = kRelFar;
+    int cnt = 0, cnt_next = 0, cnt_before = 0;
+    if (!spans) {
+      rv = tile_rel(v, ts);
+      cnt = __popcll(__ballot(rv < kTile));
+      cnt_next = __popcll(__ballot(rv < kTile - 4));
+      cnt_before = __popcll(__ballot(rv < 0));
+    }
     const bool dense = cnt == 64;
     const int k1 = k0 + cnt;
     const int kb = k0 + cnt_before;
@@ -630,10 +636,12 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
     }
     // 5. the end check (6.3) on the plain bytes before each boundary of the window in [ts-2, te)
     // (earlier ones belong to the previous tile)
-    const bool pfail = lane < cnt && rv >= -2 && incomplete_before(tb, rv);
+    const bool pfail = !spans && lane < cnt && rv >= -2 && incomplete_before(tb, rv);
     const bool any_plain = __any(m != 0u);
-    const bool tile_bad = any_plain || __any(pfail);
-    if (!tile_bad && !dense) {
+    const bool tile_bad = any_plain || (!spans && __any(pfail));
+    if (!tile_bad && spans) {
+      // the open string runs on past te; no string ends here
+    } else if (!tile_bad && !dense) {
       // 6. every string that ends in the tile is valid, but for the first detection the
       // open string may carry; those begun in this wave form [pend_lo, pend_hi), written
       // during the next tile
