@@ -365,6 +365,54 @@ def test_batch_strings_across_tiles_and_waves(u8):
         u8.set_config(**old)
 
 
+def test_batch_pieces_at_tile_edges_inside_long_strings(u8):
+    """Strings of CJK-like text spanning several 4 KiB tiles (a tile inside one string skips
+    the boundary work), each with one piece placed so that a chosen byte of it falls within
+    three bytes of a tile edge: lone continuations, leads cut short, overlong, surrogate and
+    too-large sequences, bytes F5..FF, and valid 2-, 3- and 4-byte characters cut by the
+    edge; some strings end inside a character, short strings sit between them.  Several
+    grid sizes move the edges of the waves' runs of tiles."""
+    rng = np.random.default_rng(91)
+    T = 4096
+    cjk = bytes.fromhex("e4b880")
+    pieces = [b"\x80", b"\xc3", b"\xc0\x80", b"\xe0\x80\x80", b"\xed\xa0\x80", b"\xf4\x90\x80\x80", b"\xf5",
+              b"\xe3\x82", b"\xf0\x9f\x98", b"\xe4\xb8\x80", b"\xf0\x9f\x98\x80", b"\xc3\xa9", b"\xef\xbf\xbf"]
+    parts, lens, placed = [], [], []
+    pos = 0
+    for i in range(3 * len(pieces) * 7):
+        if i % 5 == 4:  # a short string between the long ones
+            sh = b"a" * int(rng.integers(0, 6))
+            parts.append(sh); lens.append(len(sh)); pos += len(sh)
+            continue
+        piece = pieces[i % len(pieces)]
+        j = int(rng.integers(0, len(piece)))
+        target = (pos // T + 1 + int(rng.integers(0, 3))) * T + int(rng.integers(-3, 4))
+        gap = target - j - pos
+        ncjk = (gap - 1) // 3
+        body = cjk * ncjk + b"a" * (gap - 3 * ncjk) + piece + b"a" + cjk * int(rng.integers(700, 3000))
+        if rng.random() < 0.2:
+            body += b"\xe4\xb8"  # the string ends inside a character
+        placed.append((pos + gap + j, piece[j]))
+        parts.append(body); lens.append(len(body)); pos += len(body)
+    data = np.frombuffer(b"".join(parts), np.uint8).copy()
+    offsets = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    assert all(int(data[p]) == b and abs(p - round(p / T) * T) <= 3 for p, b in placed)
+    f_o, e_o = oracle.first_error_batch(data, offsets)
+    assert (f_o == 0).sum() > 30 and (f_o == 1).sum() > 30
+    td, to = dev(data), dev(offsets)
+    old = u8.get_config()
+    try:
+        for waves in (1, 3, 16, 64):
+            say(f"case: pieces at tile edges, batch_waves_per_cu {waves}")
+            u8.set_config(batch_waves_per_cu=waves)
+            flags, ferr = u8.validate_batch(td, to)
+            torch.cuda.synchronize()
+            assert np.array_equal(ferr.cpu().numpy(), e_o), waves
+            assert np.array_equal(flags.cpu().numpy(), f_o), waves
+    finally:
+        u8.set_config(**old)
+
+
 def test_batch_graph_replays(u8):
     """The captured-graph entry point: every replay, with eager work between them, equals the oracle."""
     cases = []
