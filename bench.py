@@ -324,6 +324,11 @@ def autotune_single(u8, lib, bufs, rounds=7):
             "fastest_ms_for_all_buffers": _top(cands, ms)}
 
 
+def _batch_launch(u8):
+    c = u8.get_config()
+    return {k: c[k] for k in ("batch_waves_per_cu", "batch_ascii", "batch_unroll")}
+
+
 def autotune_batch(u8, lib, td, to, n, flags, ferr, rounds=7):
     import ctypes
     best = u8.Config()
@@ -332,10 +337,12 @@ def autotune_batch(u8, lib, td, to, n, flags, ferr, rounds=7):
                                  ctypes.byref(best), times, 64)
     if k < 0:
         raise u8.Utf8vError(k, "utf8v_autotune_batch")
-    cands = [f"batch_waves_per_cu={w},batch_ascii={a}" for w in (4, 8, 12, 16, 20, 24, 32, 48, 64) for a in (0, 1)]
+    cands = [f"batch_waves_per_cu={w},batch_ascii={a},batch_unroll={u}"
+             for w in (4, 8, 12, 16, 20, 24, 32, 48, 64) for a in (0, 1) for u in (4, 8)]
     ms = np.array([times[i] for i in range(k)])
     log(f"autotuned batch launch: {best.as_dict()}")
-    return {"chosen": {"batch_waves_per_cu": best.batch_waves_per_cu, "batch_ascii": best.batch_ascii},
+    return {"chosen": {"batch_waves_per_cu": best.batch_waves_per_cu, "batch_ascii": best.batch_ascii,
+                       "batch_unroll": best.batch_unroll},
             "rounds": rounds, "fastest_ms_x3": _top(cands, ms)}
 
 
@@ -425,7 +432,7 @@ def bench_batch(u8, lib, synth, torch, dev, stream, sh, args):
             "algorithmic_GBps_warm": round(algo / warm / 1e9, 1),
             "per_string_launch_strings_per_s": round(per_string) if per_string else None,
             "speedup_vs_per_string_launch": round(nstr / warm / per_string, 1) if per_string else None,
-            "graph": graph, "autotune": tuned, "launch": {"batch_waves_per_cu": u8.get_config()["batch_waves_per_cu"]}}
+            "graph": graph, "autotune": tuned, "launch": _batch_launch(u8)}
 
 
 def bench_graph(u8, lib, torch, td, to, flags, ferr, nstr, offsets, expected, stream, sh, reps, warm):
@@ -598,7 +605,7 @@ def bench_heavy(u8, lib, synth, torch, dev, stream, sh, args):
             row["autotune"]["tuning_seed"] = 13
             del t_data, t_off, t_td, t_to, t_flags, t_ferr
             torch.cuda.empty_cache()
-        row["launch"] = {"batch_waves_per_cu": u8.get_config()["batch_waves_per_cu"]}
+        row["launch"] = _batch_launch(u8)
         for mode, fn in (("direct", lib.utf8v_validate_batch_async), ("graph", lib.utf8v_validate_batch_graph)):
             def run():
                 rc = fn(td.data_ptr(), to.data_ptr(), n, flags.data_ptr(), ferr.data_ptr(), sh)
@@ -647,7 +654,7 @@ def bench_paper_shaped(u8, lib, synth, torch, dev, stream, sh, args):
         tuned["tuning_seed"] = 60
         del t_data, t_off, t_td, t_to
         torch.cuda.empty_cache()
-    launch = {"batch_waves_per_cu": u8.get_config()["batch_waves_per_cu"]}
+    launch = _batch_launch(u8)
     for i, variant in enumerate(("unif1", "unif2", "unif3", "unif4")):
         data, offsets, _ = synth.batch_from_lengths(np.full(n, length, np.int64), variant, 40 + i)
         td = torch.from_numpy(data).to(dev)

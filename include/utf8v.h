@@ -303,8 +303,11 @@ typedef struct {
   int32_t ascii;             /* 1: skip classification of all-ASCII wave tiles (section 6.4; tested per
                                 tile of `unroll` KiB, with an exponential back-off after a non-ASCII one) */
   int32_t batch_waves_per_cu; /* batch: persistent one-wave workgroups per compute unit, 1..64 */
-  int32_t batch_ascii;       /* batch: 1 = skip the classification of all-ASCII 4 KiB tiles (section 6.4,
+  int32_t batch_ascii;       /* batch: 1 = skip the classification of all-ASCII wave tiles (section 6.4,
                                 with the same back-off as the single-buffer kernel) */
+  int32_t batch_unroll;      /* batch: 1 KiB slabs per wave tile (the bytes a lane checks per tile / 16),
+                                4 or 8; an 8 KiB tile halves the per-tile work on long strings and needs
+                                twice the LDS per wave */
 } utf8v_config;
 
 /* Read / replace the launch configuration of the calling process (all devices). */
@@ -326,8 +329,9 @@ int utf8v_autotune_single(const uint8_t *const *bufs, const size_t *lens, int nb
 
 /*
  * utf8v_autotune_batch -- the same for the batch kernel: persistent grid (4..64
- * one-wave workgroups per CU) x section 6.4 ASCII test (off/on), on a sample CSR
- * batch (device memory, with output arrays of n entries the timing runs overwrite).
+ * one-wave workgroups per CU) x section 6.4 ASCII test (off/on) x wave tile (4 or
+ * 8 KiB), on a sample CSR batch (device memory, with output arrays of n entries the
+ * timing runs overwrite).
  */
 int utf8v_autotune_batch(const uint8_t *data, const int64_t *offsets, int64_t n, uint8_t *out_flags,
                          int64_t *out_first_err, int rounds, utf8v_config *best, float *times_ms, int max_times);

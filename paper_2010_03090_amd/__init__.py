@@ -263,7 +263,8 @@ def get_config() -> dict:
 
 
 def set_config(**kw) -> dict:
-    """Update launch parameters (unroll, waves_per_cu, ascii, batch_waves_per_cu, batch_ascii)."""
+    """Update launch parameters (unroll, waves_per_cu, ascii, batch_waves_per_cu, batch_ascii,
+    batch_unroll)."""
     c = Config()
     check(load().utf8v_get_config(ctypes.byref(c)), "utf8v_get_config")
     for k, v in kw.items():

@@ -24,7 +24,8 @@ _i32, _i64, _sz, _vp = ctypes.c_int, ctypes.c_int64, ctypes.c_size_t, ctypes.c_v
 
 class Config(ctypes.Structure):
     _fields_ = [("unroll", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32), ("ascii", ctypes.c_int32),
-                ("batch_waves_per_cu", ctypes.c_int32), ("batch_ascii", ctypes.c_int32)]
+                ("batch_waves_per_cu", ctypes.c_int32), ("batch_ascii", ctypes.c_int32),
+                ("batch_unroll", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -26,7 +26,7 @@ thread_local int g_last_status = UTF8V_OK;
 thread_local int g_last_hip = 0;
 
 std::mutex g_mu;
-utf8v_config g_cfg = {4, 20, 1, 16, 1};
+utf8v_config g_cfg = {4, 20, 1, 16, 1, 4};
 
 constexpr int kBatchSlotsPerCu = 64;  // = the largest batch_waves_per_cu
 
@@ -151,6 +151,7 @@ utf8v::TuneBatch tune_batch() {
   utf8v::TuneBatch t;
   t.waves_per_cu = g_cfg.batch_waves_per_cu;
   t.ascii = g_cfg.batch_ascii;
+  t.unroll = g_cfg.batch_unroll;
   return t;
 }
 
@@ -514,7 +515,8 @@ int utf8v_set_config(const utf8v_config* cfg) {
   const bool ok = (cfg->unroll == 1 || cfg->unroll == 2 || cfg->unroll == 4 || cfg->unroll == 8) &&
                   cfg->waves_per_cu >= 1 && cfg->waves_per_cu <= 4096 && (cfg->ascii == 0 || cfg->ascii == 1) &&
                   cfg->batch_waves_per_cu >= 1 && cfg->batch_waves_per_cu <= 64 &&
-                  (cfg->batch_ascii == 0 || cfg->batch_ascii == 1);
+                  (cfg->batch_ascii == 0 || cfg->batch_ascii == 1) &&
+                  (cfg->batch_unroll == 4 || cfg->batch_unroll == 8);
   if (!ok) return set_status(UTF8V_EINVAL);
   std::lock_guard<std::mutex> lk(g_mu);
   g_cfg = *cfg;

@@ -43,11 +43,13 @@ namespace utf8v {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kU = 4;                        // 1 KiB slabs per wave tile (one per byte lane of the plain check)
-static_assert(kU == 4, "the plain check transposes four slabs across the byte lanes");
-constexpr int kTile = kU * 1024;             // bytes per tile (one wave)
+// A wave tile is U 1 KiB slabs, U = 4 or 8 (a launch setting): the plain check transposes
+// four slabs at a time across the byte lanes.
 constexpr int kPad = 16;                     // bytes kept before the tile in its LDS buffer
-constexpr int kBufBytes = kPad + kTile + 16;  // ... and room for reads that run just past its end
+template <int U>
+constexpr int kTileOf = U * 1024;            // bytes per tile (one wave)
+template <int U>
+constexpr int kBufOf = kPad + kTileOf<U> + 16;  // LDS buffer: the tile, and room for reads just past its end
 constexpr int kGroupChunks = 16;             // 16-byte chunks checked again per pass (a dword per lane)
 constexpr int32_t kNonePos = INT32_MAX;      // no detection (tile-relative positions)
 constexpr int kNonTemporal = 2;              // cache policy of the tile loads: streamed once
@@ -243,25 +245,27 @@ __device__ __forceinline__ u32x4 edge_mask(u32x4 v, int64_t c, int64_t lo, int64
   return u32x4{w[0], w[1], w[2], w[3]};
 }
 
-// A tile whose bytes all lie in the batch range: its four 1 KiB slabs go from global
-// memory straight into the LDS buffer (lane l's 16 bytes of slab u to byte
-// kPad + u*1024 + 16*l), read once.
+// A tile whose bytes all lie in the batch range: its 1 KiB slabs go from global memory
+// straight into the LDS buffer (lane l's 16 bytes of slab u to byte kPad + u*1024 + 16*l),
+// read once.
+template <int U>
 __device__ __forceinline__ void dma_tile(gptr<const uint8_t> data, int64_t ts, uint8_t* buf, int lane) {
 #pragma unroll
-  for (int u = 0; u < kU; ++u)
+  for (int u = 0; u < U; ++u)
     __builtin_amdgcn_global_load_lds((gptr<const void>)(sgpr_base(data + ts + u * 1024) + lane * 16),
                                      (lptr<void>)(buf + kPad + u * 1024), 16, 0, kNonTemporal);
 }
 
 // A tile at an edge of the batch range: the chunks that hold batch bytes are read, the
 // bytes outside [lo, hi) set to zero, and the result stored to the LDS buffer.
+template <int U>
 __device__ __forceinline__ void edge_tile(gptr<const uint8_t> data, int64_t ts, int64_t lo, int64_t hi, uint8_t* buf,
                                           int lane) {
-  u32x4 x[kU];
+  u32x4 x[U];
 #pragma unroll
-  for (int u = 0; u < kU; ++u) x[u] = edge_load(data, ts + u * 1024 + lane * 16, lo, hi);
+  for (int u = 0; u < U; ++u) x[u] = edge_load(data, ts + u * 1024 + lane * 16, lo, hi);
 #pragma unroll
-  for (int u = 0; u < kU; ++u)
+  for (int u = 0; u < U; ++u)
     reinterpret_cast<u32x4*>(buf + kPad + u * 1024)[lane] = edge_mask(x[u], ts + u * 1024 + lane * 16, lo, hi);
 }
 
@@ -349,7 +353,8 @@ struct TileBytes {
 struct TileRuns {
   int64_t tiles;
   int per;
-  __device__ int wave_of(int64_t p, int64_t c0) const { return (int)((p - c0) / kTile) / per; }
+  int tile;  // bytes per tile
+  __device__ int wave_of(int64_t p, int64_t c0) const { return (int)((p - c0) / tile) / per; }
 };
 
 // Cross-wave slot word: arrivals in bits 40..63 and, in bits 0..39, the least partial
@@ -416,14 +421,21 @@ __device__ __forceinline__ void cross_wave_end(const DevArgs& a, const CrossWave
 }
 
 // The 16-byte chunks of a tile that reported a plain error: chunk q (tile position
-// 16q, q = 64u + lane) is bit q of the 256-bit mask m[0..3].  Wave-uniform.
+// 16q, q = 64u + lane) is bit q of the mask m[0..U-1].  Wave-uniform.
+template <int U>
 struct BadChunks {
-  uint64_t m0, m1, m2, m3;
+  uint64_t m[U];
   // The first chunk q' >= q with q' < q_end, or -1.
   __device__ __forceinline__ int next(int q, int q_end) const {
     for (; q < q_end; q = (q & ~63) + 64) {
       const int u = q >> 6;
-      const uint64_t w = (u == 0 ? m0 : u == 1 ? m1 : u == 2 ? m2 : m3) & (~0ull << (q & 63));
+      uint64_t w;
+      if constexpr (U == 4)
+        w = (u == 0 ? m[0] : u == 1 ? m[1] : u == 2 ? m[2] : m[3]) & (~0ull << (q & 63));
+      else
+        w = (u < 4 ? (u == 0 ? m[0] : u == 1 ? m[1] : u == 2 ? m[2] : m[3])
+                   : (u == 4 ? m[4] : u == 5 ? m[5] : u == 6 ? m[6] : m[7])) &
+            (~0ull << (q & 63));
       if (w) {
         const int r = (q & ~63) + (int)__builtin_ctzll(w);
         return r < q_end ? r : -1;
@@ -437,13 +449,13 @@ struct BadChunks {
 // lane's chunk of slab u holds a flagged position.  A tile that is all ASCII with an
 // ASCII halo cannot hold an error (6.4); a tile without bytes >= 0xE0 (nor in the dword
 // before each chunk) takes the short form of the checks, which flags the same positions.
-template <bool ASCII>
-__device__ __forceinline__ uint32_t plain_check(const u32x4 (&x)[kU], const uint32_t (&prev)[kU], AsciiBackoff& ascii,
+template <bool ASCII, int U>
+__device__ __forceinline__ uint32_t plain_check(const u32x4 (&x)[U], const uint32_t (&prev)[U], AsciiBackoff& ascii,
                                                 AsciiBackoff& two) {
   if (ASCII && ascii.due()) {
     uint32_t o = 0;
 #pragma unroll
-    for (int u = 0; u < kU; ++u) o |= x[u].x | x[u].y | x[u].z | x[u].w | prev[u];
+    for (int u = 0; u < U; ++u) o |= x[u].x | x[u].y | x[u].z | x[u].w | prev[u];
     const bool all_ascii = __all((o & 0x80808080u) == 0);
     ascii.result(all_ascii);
     if (all_ascii) return 0u;
@@ -452,28 +464,31 @@ __device__ __forceinline__ uint32_t plain_check(const u32x4 (&x)[kU], const uint
   if (two.due()) {
     uint32_t o = 0;
 #pragma unroll
-    for (int u = 0; u < kU; ++u) o |= ge_e0(x[u].x) | ge_e0(x[u].y) | ge_e0(x[u].z) | ge_e0(x[u].w) | ge_e0(prev[u]);
+    for (int u = 0; u < U; ++u) o |= ge_e0(x[u].x) | ge_e0(x[u].y) | ge_e0(x[u].z) | ge_e0(x[u].w) | ge_e0(prev[u]);
     short_form = __all((o & 0x80808080u) == 0);
     two.result(short_form);
   }
   uint32_t m = 0;
   if (short_form) {
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < U; ++u) {
       const uint32_t e = two_byte_errors(x[u].x, prev[u]) | two_byte_errors(x[u].y, x[u].x) |
                          two_byte_errors(x[u].z, x[u].y) | two_byte_errors(x[u].w, x[u].z);
       m |= (e & 0x80808080u) ? 1u << u : 0u;
     }
-  } else {  // byte lane u of the transposed check's result belongs to slab u
+  } else {  // byte lane j of the transposed check's result of slabs g..g+3 belongs to slab g + j
     m = nonzero_bytes(chunks4_errors(0u, x[0], x[1], x[2], x[3], prev[0], prev[1], prev[2], prev[3]));
+    if constexpr (U == 8)
+      m |= nonzero_bytes(chunks4_errors(0u, x[4], x[5], x[6], x[7], prev[4], prev[5], prev[6], prev[7])) << 4;
   }
   return m;
 }
 
-// A lane's four 16-byte chunks of the tile in LDS and the dword before each.
-__device__ __forceinline__ void read_tile(const uint8_t* tb, int lane, u32x4 (&x)[kU], uint32_t (&prev)[kU]) {
+// A lane's 16-byte chunks of the tile in LDS (one per slab) and the dword before each.
+template <int U>
+__device__ __forceinline__ void read_tile(const uint8_t* tb, int lane, u32x4 (&x)[U], uint32_t (&prev)[U]) {
 #pragma unroll
-  for (int u = 0; u < kU; ++u) {
+  for (int u = 0; u < U; ++u) {
     x[u] = reinterpret_cast<const u32x4*>(tb + u * 1024)[lane];
     prev[u] = *reinterpret_cast<const uint32_t*>(tb + u * 1024 + lane * 16 - 4);
   }
@@ -483,8 +498,12 @@ __device__ __forceinline__ void read_tile(const uint8_t* tb, int lane, u32x4 (&x
 // the boundary window of tile t+1 are requested right after tile t's boundary scan, so
 // their latency overlaps tile t's checks.  Lane l of a window holds boundary kw + l, the
 // end of string kw + l - 1 and the start of string kw + l.
-template <bool ASCII>
+template <bool ASCII, int U>
 __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
+  static_assert(U == 4 || U == 8, "the plain check transposes four slabs at a time");
+  constexpr int kU = U;
+  constexpr int kTile = kTileOf<U>;
+  constexpr int kBufBytes = kBufOf<U>;
   const DevArgs a = args_of(a0);
   __shared__ __align__(16) uint8_t sbuf[2][kBufBytes];  // tile buffers: the tile at kPad, the 16 bytes before it at 0
   __shared__ uint32_t sflag[64];                         // flagged dwords of the error path: position | flags << 16
@@ -543,7 +562,7 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
   // the short form for 1- and 2-byte text, first tested on the wave's fourth tile: a wave
   // of a batch of short mixed strings has few tiles and would pay for a test in half of them
   AsciiBackoff two{3, 7};
-  const uint32_t m_first = plain_check<ASCII>(x, prev, ascii, two);
+  const uint32_t m_first = plain_check<ASCII, U>(x, prev, ascii, two);
   asm volatile("" : "+v"(pr.pv) : "v"(m_first));  // the probe's value is used after the check
   // String indices are 32-bit: a batch holds fewer than 2^31 - 64 strings (the host checks).
   const int n32 = (int)n;
@@ -591,7 +610,7 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
     const uint8_t* const tb = buf + kPad;  // tb[p - ts] = byte p, for p >= ts - kPad
     // 1. this tile's bytes and boundary window have arrived (requested during the previous tile)
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    if (edge_cur) edge_tile(data, ts, lo_v, hi_v, buf, lane);
+    if (edge_cur) edge_tile<U>(data, ts, lo_v, hi_v, buf, lane);
     // 2. boundaries of the window [ts-4, te): [k0, k1), those in [ts, te): [kb, k1).  Lane l
     // holds boundary k0 + l, as a 32-bit position relative to ts.  A tile inside one string
     // (the window's first boundary, lane 0's, lies past it) has none, and skips this and
@@ -612,7 +631,7 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
     const int64_t vwin = v;
     if (t + 1 == t_end && !dense) final_en_v = in_vgpr(lane_at64(vwin, cnt));  // first boundary >= te
     // the tile for the checks: each lane's four 16-byte chunks and the dword before each
-    read_tile(tb, lane, x, prev);
+    read_tile<U>(tb, lane, x, prev);
     // 3. requests for tile t+1 (its bytes, its window: boundaries from k0 + cnt_next on; a
     // dense tile's comes after its error path), then the previous tile's valid strings: a
     // load's wait also waits for every store issued before it, so these stores get a
@@ -620,7 +639,7 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
     bool edge_next = false;
     if (t + 1 < t_end) {
       edge_next = t + 1 < t_in_first || t + 1 > t_in_last;
-      if (!edge_next) dma_tile(data, te, nbuf, lane);
+      if (!edge_next) dma_tile<U>(data, te, nbuf, lane);
       if (!dense && cnt_next > 0) v = load_window(offsets, k0 + cnt_next, n32, lane);
     }
     if (lane == 63) *reinterpret_cast<u32x4*>(nbuf) = x[kU - 1];  // the 16 bytes before tile t+1
@@ -632,7 +651,7 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
       m = m_first;
       first_tile = false;
     } else {
-      m = plain_check<ASCII>(x, prev, ascii, two);
+      m = plain_check<ASCII, U>(x, prev, ascii, two);
     }
     // 5. the end check (6.3) on the plain bytes before each boundary of the window in [ts-2, te)
     // (earlier ones belong to the previous tile)
@@ -672,8 +691,11 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
       // 7. rare: first detections string by string, window by window (a dense tile has
       // several).  Lane l's string ends at the lane's boundary e and starts at the previous
       // one s (lane 0: the open string's start, or the last boundary of the previous window).
-      BadChunks bad{0, 0, 0, 0};
-      if (any_plain) bad = BadChunks{in_vgpr(__ballot(m & 1u)), in_vgpr(__ballot(m & 2u)), in_vgpr(__ballot(m & 4u)), in_vgpr(__ballot(m & 8u))};
+      BadChunks<U> bad{};
+      if (any_plain) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) bad.m[u] = in_vgpr(__ballot(m & (1u << u)));
+      }
       int kw = k0;          // boundary of lane 0
       int64_t vcur = vwin;  // the lane's boundary
       int32_t e = rv;       // ... tile-relative
@@ -815,7 +837,7 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
   // and the one still open, which runs into the next wave
   if (lane0 && (first_k >= 0 || open_k >= 0)) {
     const int64_t tiles_u = (uniform(hi_v) + 1 - c0 + kTile - 1) / kTile;
-    const TileRuns runs_u{tiles_u, (int)((tiles_u + gridDim.x - 1) / gridDim.x)};
+    const TileRuns runs_u{tiles_u, (int)((tiles_u + gridDim.x - 1) / gridDim.x), kTile};
     CrossWave c1 = cross_wave_begin(first_k, uniform(first_st_v), uniform(first_en_v), uniform(first_d_v), c0, runs_u);
     CrossWave c2 = cross_wave_begin(open_k, uniform(open_st_v), uniform(final_en_v), open_d, c0, runs_u);
     cross_wave_arrive(a, c1, false);
@@ -861,21 +883,31 @@ BatchArgs batch_args(const uint8_t* data, const int64_t* offsets, int64_t n, uin
   return a;
 }
 
-// One-wave workgroups of batch_main that a CU holds at once (its registers decide);
-// asked once per process, when a stream's workspace is made and before the graph
-// form's capture, so never while a stream is being captured.
-template <bool ASCII>
+// The kernel of a launch setting: ASCII test on or off, 4 or 8 KiB tiles.
+static const void* batch_kernel(const TuneBatch& cfg) {
+  if (cfg.unroll == 8)
+    return cfg.ascii ? reinterpret_cast<const void*>(batch_main<true, 8>)
+                     : reinterpret_cast<const void*>(batch_main<false, 8>);
+  return cfg.ascii ? reinterpret_cast<const void*>(batch_main<true, 4>)
+                   : reinterpret_cast<const void*>(batch_main<false, 4>);
+}
+
+// One-wave workgroups of batch_main that a CU holds at once (its registers and LDS
+// decide); asked once per process and kernel, when a stream's workspace is made and
+// before the graph form's capture, so never while a stream is being captured.
+template <bool ASCII, int U>
 static int resident_waves_per_cu_t() {
   static const int resident = [] {
     int blocks = 0;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_main<ASCII>, 64, 0) == hipSuccess ? blocks
-                                                                                                       : 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_main<ASCII, U>, 64, 0) == hipSuccess ? blocks
+                                                                                                          : 0;
   }();
   return resident;
 }
 
-static int resident_waves_per_cu(bool ascii) {
-  return ascii ? resident_waves_per_cu_t<true>() : resident_waves_per_cu_t<false>();
+static int resident_waves_per_cu(const TuneBatch& cfg) {
+  if (cfg.unroll == 8) return cfg.ascii ? resident_waves_per_cu_t<true, 8>() : resident_waves_per_cu_t<false, 8>();
+  return cfg.ascii ? resident_waves_per_cu_t<true, 4>() : resident_waves_per_cu_t<false, 4>();
 }
 
 // One persistent grid of one-wave workgroups: num_cus * waves_per_cu of them, whatever
@@ -885,28 +917,42 @@ static int batch_grid(const TuneBatch& cfg, int num_cus) {
 }
 
 static int batch_level(const TuneBatch& cfg) {
-  return (cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1) <= resident_waves_per_cu(cfg.ascii != 0) ? 1 : 0;
+  return (cfg.waves_per_cu > 0 ? cfg.waves_per_cu : 1) <= resident_waves_per_cu(cfg) ? 1 : 0;
 }
 
 hipError_t launch_batch(const BatchArgs& a, const TuneBatch& cfg, int num_cus, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
   if (a.n > kMaxBatchStrings) return hipErrorInvalidValue;
-  if (cfg.ascii)
-    hipLaunchKernelGGL(batch_main<true>, dim3(batch_grid(cfg, num_cus)), dim3(64), 0, st, a, batch_level(cfg));
-  else
-    hipLaunchKernelGGL(batch_main<false>, dim3(batch_grid(cfg, num_cus)), dim3(64), 0, st, a, batch_level(cfg));
+  const dim3 grid(batch_grid(cfg, num_cus)), block(64);
+  const int level = batch_level(cfg);
+  if (cfg.unroll == 8) {
+    if (cfg.ascii)
+      hipLaunchKernelGGL((batch_main<true, 8>), grid, block, 0, st, a, level);
+    else
+      hipLaunchKernelGGL((batch_main<false, 8>), grid, block, 0, st, a, level);
+  } else {
+    if (cfg.ascii)
+      hipLaunchKernelGGL((batch_main<true, 4>), grid, block, 0, st, a, level);
+    else
+      hipLaunchKernelGGL((batch_main<false, 4>), grid, block, 0, st, a, level);
+  }
   return hipGetLastError();
 }
 
 void batch_launch_queries() {
-  (void)resident_waves_per_cu(true);
-  (void)resident_waves_per_cu(false);
+  for (int u : {4, 8})
+    for (int asc : {0, 1}) {
+      TuneBatch t;
+      t.unroll = u;
+      t.ascii = asc;
+      (void)resident_waves_per_cu(t);
+    }
 }
 
 // Kernel node parameters of one batch launch; args[] must stay alive while they are used.
 static hipKernelNodeParams batch_node_params(void** args, const TuneBatch& cfg, int num_cus) {
   hipKernelNodeParams p{};
-  p.func = cfg.ascii ? reinterpret_cast<void*>(batch_main<true>) : reinterpret_cast<void*>(batch_main<false>);
+  p.func = const_cast<void*>(batch_kernel(cfg));
   p.gridDim = dim3(batch_grid(cfg, num_cus));
   p.blockDim = dim3(64);
   p.sharedMemBytes = 0;

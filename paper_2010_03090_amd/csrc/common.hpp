@@ -22,6 +22,7 @@ struct TuneSingle {
 struct TuneBatch {
   int waves_per_cu = 16;      // persistent grid: one-wave workgroups per compute unit
   int ascii = 1;              // section 6.4 test of all-ASCII tiles (with its back-off)
+  int unroll = 4;             // 1 KiB slabs per wave tile: 4 or 8
 };
 
 // State word of a single-buffer call: arrivals << kStateShift | least detection

@@ -295,6 +295,7 @@ int GpuBackend::launch(uint64_t first, uint64_t count) {
     utf8v_get_config(&c);
     tb.waves_per_cu = c.batch_waves_per_cu;
     tb.ascii = c.batch_ascii;
+    tb.unroll = c.batch_unroll;
     const ServeRequest& r0 = slot(first);
     e = utf8v::launch_batch(batch_args(data, offs, plan.strings, direct ? r0.flags : flags,
                                        direct ? r0.errs : errs, wslots),
@@ -542,6 +543,7 @@ int utf8v_serve_replay(const utf8v_server_config* cfg, int mode, const uint8_t* 
   TuneBatch tb;
   tb.waves_per_cu = c.batch_waves_per_cu;
   tb.ascii = c.batch_ascii;
+  tb.unroll = c.batch_unroll;
   const int64_t t0 = now_ns() + 2000000;
   for (int64_t i = 0; i < nreq && e == hipSuccess; ++i) {
     wait_until(t0 + arrival_ns[i]);

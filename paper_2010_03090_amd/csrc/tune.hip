@@ -111,12 +111,14 @@ int utf8v_autotune_batch(const uint8_t* data, const int64_t* offsets, int64_t n,
   utf8v_get_config(&base);
   std::vector<utf8v_config> cand;
   for (int w : {4, 8, 12, 16, 20, 24, 32, 48, 64})
-    for (int a : {0, 1}) {
-      utf8v_config c = base;
-      c.batch_waves_per_cu = w;
-      c.batch_ascii = a;
-      cand.push_back(c);
-    }
+    for (int a : {0, 1})
+      for (int u : {4, 8}) {
+        utf8v_config c = base;
+        c.batch_waves_per_cu = w;
+        c.batch_ascii = a;
+        c.batch_unroll = u;
+        cand.push_back(c);
+      }
   hipStream_t st = nullptr;
   std::vector<double> med;
   const int b = time_candidates(

@@ -86,3 +86,24 @@ def test_library_is_in_tree_and_for_gfx950():
     assert os.path.dirname(_native.LIB_PATH) == os.path.join(ROOT, "paper_2010_03090_amd")
     blob = open(_native.LIB_PATH, "rb").read()
     assert b"gfx950" in blob
+
+
+def test_launch_configuration_defaults_and_checks():
+    """utf8v_config: the defaults, and settings outside the documented ranges refused (host only)."""
+    lib = _native.load()
+    c = _native.Config()
+    assert lib.utf8v_get_config(ctypes.byref(c)) == 0
+    saved = cfg_dict(c)
+    assert (c.batch_ascii, c.batch_unroll) in {(0, 4), (1, 4), (0, 8), (1, 8)}
+    try:
+        for field, bad in (("unroll", 3), ("waves_per_cu", 0), ("ascii", 2), ("batch_waves_per_cu", 65),
+                           ("batch_ascii", -1), ("batch_unroll", 2), ("batch_unroll", 6), ("batch_unroll", 16)):
+            x = _native.Config(**{**saved, field: bad})
+            assert lib.utf8v_set_config(ctypes.byref(x)) == _native.UTF8V_EINVAL, (field, bad)
+            assert lib.utf8v_get_config(ctypes.byref(c)) == 0 and cfg_dict(c) == saved
+        for u in (8, 4):
+            x = _native.Config(**{**saved, "batch_unroll": u})
+            assert lib.utf8v_set_config(ctypes.byref(x)) == 0
+            assert lib.utf8v_get_config(ctypes.byref(c)) == 0 and c.batch_unroll == u
+    finally:
+        lib.utf8v_set_config(ctypes.byref(_native.Config(**saved)))

@@ -16,6 +16,16 @@ from paper_2010_03090_amd import synth
 
 pytestmark = pytest.mark.gpu
 
+
+@pytest.fixture(params=[4, 8], ids=["tile4k", "tile8k"])
+def batch_tile(u8, request):
+    """Run a batch test with 4 KiB and with 8 KiB wave tiles (the batch kernel's tile setting)."""
+    old = u8.get_config()
+    u8.set_config(batch_unroll=request.param)
+    say(f"batch tile {request.param} KiB")
+    yield request.param
+    u8.set_config(**old)
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))  # the repository root
 
 torch = pytest.importorskip("torch")
@@ -240,7 +250,7 @@ def test_config1_full_size_1gib(u8, variant):
     torch.cuda.empty_cache()
 
 
-def test_batch_exhaustive_short_strings(u8):
+def test_batch_exhaustive_short_strings(u8, batch_tile):
     """Every string of length 0..3 in one CSR batch (each at many alignments)."""
     say("case: batch exhaustive <= 3")
     parts, lens = [], []
@@ -262,7 +272,7 @@ def test_batch_exhaustive_short_strings(u8):
     assert np.array_equal(flags.cpu().numpy(), f_o)
 
 
-def test_batch_semantics(u8):
+def test_batch_semantics(u8, batch_tile):
     """offsets[0] != 0, empty strings, strings across tiles, and each string alone == in the batch."""
     rng = np.random.default_rng(5)
     lens = np.concatenate([rng.integers(0, 9, 400), rng.integers(0, 5000, 40), [0, 0, 1, 0, 70000, 0]])
@@ -284,7 +294,7 @@ def test_batch_semantics(u8):
             assert alone == ferr[k]
 
 
-def test_batch_random_bytes_and_tiny_strings(u8):
+def test_batch_random_bytes_and_tiny_strings(u8, batch_tile):
     rng = np.random.default_rng(8)
     lens = rng.integers(0, 6, 200_000)
     offsets = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
@@ -297,7 +307,7 @@ def test_batch_random_bytes_and_tiny_strings(u8):
     assert np.array_equal(flags.cpu().numpy(), f_o)
 
 
-def test_batch_config2_full_size(u8):
+def test_batch_config2_full_size(u8, batch_tile):
     """1,000,000 log-normal strings (median 64 B, sigma 1.2), 1% with an injected error."""
     say("case: config2")
     data, offsets, expected = synth.lognormal_batch(1_000_000, 2)
@@ -310,7 +320,7 @@ def test_batch_config2_full_size(u8):
     assert int((f_o == 0).sum()) >= 10_000
 
 
-def test_batch_config3_heavy_tail(u8):
+def test_batch_config3_heavy_tail(u8, batch_tile):
     """20,000 Pareto strings (alpha 1.1, 1 KiB .. 64 MiB), per-string variants, 0.5% errors."""
     say("case: config3a")
     data, offsets, expected = synth.pareto_batch(20_000, 3)
@@ -322,7 +332,7 @@ def test_batch_config3_heavy_tail(u8):
     assert np.array_equal(e_o[expected >= 0], expected[expected >= 0])
 
 
-def test_batch_config3_heavy_tail_4gib(u8):
+def test_batch_config3_heavy_tail_4gib(u8, batch_tile):
     """The heavy tail at x_m 34 KiB: 20,000 Pareto strings, about 4.3 GB, strings up to 64 MiB."""
     say("case: config3b generate")
     data, offsets, expected = synth.pareto_batch(20_000, 3, xm=34 * 1024)
@@ -340,7 +350,7 @@ def test_batch_config3_heavy_tail_4gib(u8):
     torch.cuda.empty_cache()
 
 
-def test_batch_strings_across_tiles_and_waves(u8):
+def test_batch_strings_across_tiles_and_waves(u8, batch_tile):
     """Strings that span several 4 KiB tiles and several waves, errors near every kind of edge."""
     rng = np.random.default_rng(17)
     lens = np.concatenate([[4095, 4096, 4097, 8191, 8192, 8193, 12289, 0, 1, 2, 3, 0, 0],
@@ -365,7 +375,7 @@ def test_batch_strings_across_tiles_and_waves(u8):
         u8.set_config(**old)
 
 
-def test_batch_pieces_at_tile_edges_inside_long_strings(u8):
+def test_batch_pieces_at_tile_edges_inside_long_strings(u8, batch_tile):
     """Strings of CJK-like text spanning several 4 KiB tiles (a tile inside one string skips
     the boundary work), each with one piece placed so that a chosen byte of it falls within
     three bytes of a tile edge: lone continuations, leads cut short, overlong, surrogate and
@@ -413,7 +423,7 @@ def test_batch_pieces_at_tile_edges_inside_long_strings(u8):
         u8.set_config(**old)
 
 
-def test_batch_graph_replays(u8):
+def test_batch_graph_replays(u8, batch_tile):
     """The captured-graph entry point: every replay, with eager work between them, equals the oracle."""
     cases = []
     for seed, n in ((21, 50_000), (22, 7), (23, 3_000), (24, 1)):
@@ -509,8 +519,10 @@ def test_tuning_invariance(u8):
                 for waves in (1, 3, 16, 4096):
                     # batch grids of 24 and 64 waves per CU exceed the resident waves (no priority levels)
                     bwaves = {1: 1, 3: 24, 16: 7, 4096: 64}[waves]
+                    # the batch tile: 8 KiB with unroll 2 and 8, 4 KiB with 1 and 4 (both with every grid)
                     u8.set_config(unroll=unroll, ascii=ascii_, waves_per_cu=waves,
-                                  batch_waves_per_cu=bwaves, batch_ascii=ascii_)
+                                  batch_waves_per_cu=bwaves, batch_ascii=ascii_,
+                                  batch_unroll=8 if unroll in (2, 8) else 4)
                     for t, e in zip(tb, expected):
                         assert u8.first_error(t) == e, (unroll, ascii_, waves)
                     flags, ferr = u8.validate_batch(td, to)
@@ -747,7 +759,7 @@ def test_async_calls_captured_in_a_torch_graph(u8):
         assert u8.first_error(tb) == exp          # eager work between replays
 
 
-def test_batch_many_empty_strings(u8):
+def test_batch_many_empty_strings(u8, batch_tile):
     """Runs of empty strings (many boundaries at one position) between non-empty ones."""
     rng = np.random.default_rng(62)
     lens = np.zeros(200_000, np.int64)
@@ -807,7 +819,7 @@ def _exhaustive_short_batch():
     return np.concatenate(parts), np.array(lens, np.int64)
 
 
-def test_batch_exhaustive_short_strings_at_shifted_alignments(u8):
+def test_batch_exhaustive_short_strings_at_shifted_alignments(u8, batch_tile):
     """Every string of 1..3 bytes, with the whole batch shifted against 16-byte chunks, 1 KiB slabs
     and 4 KiB tiles (a prefix of k bytes before offsets[0])."""
     data, lens = _exhaustive_short_batch()
@@ -822,7 +834,7 @@ def test_batch_exhaustive_short_strings_at_shifted_alignments(u8):
         assert np.array_equal(flags.cpu().numpy(), f_o), k
 
 
-def test_batch_subrange_with_invalid_bytes_around(u8):
+def test_batch_subrange_with_invalid_bytes_around(u8, batch_tile):
     """A batch over [lo, hi) of a larger buffer whose bytes outside the range would change the
     results if read: lead bytes before lo, continuation bytes after hi that complete a truncated
     last string.  Errors at the first and last bytes of the range, both edges at many offsets
@@ -851,7 +863,7 @@ def test_batch_subrange_with_invalid_bytes_around(u8):
     assert cases == 63
 
 
-def test_batch_two_byte_text_with_longer_characters_and_errors(u8):
+def test_batch_two_byte_text_with_longer_characters_and_errors(u8, batch_tile):
     """Batches of 1- and 2-byte text take a short form of the plain checks per tile; a byte
     >= 0xE0 in a tile or in the three bytes before a chunk must send the tile to the full
     checks.  Pieces are placed across chunk, slab and tile edges: 3- and 4-byte characters
@@ -883,7 +895,7 @@ def test_batch_two_byte_text_with_longer_characters_and_errors(u8):
         assert np.array_equal(flags.cpu().numpy(), f_o), trial
 
 
-def test_batch_boundary_alphabet_length_4_and_5(u8):
+def test_batch_boundary_alphabet_length_4_and_5(u8, batch_tile):
     """All strings of length 4 and 5 over the 27 boundary bytes of the byte-range table."""
     alpha = np.array([0x00, 0x41, 0x7F, 0x80, 0x8F, 0x90, 0x9F, 0xA0, 0xBF, 0xC0, 0xC1, 0xC2, 0xDF, 0xE0,
                       0xE1, 0xEC, 0xED, 0xEE, 0xEF, 0xF0, 0xF1, 0xF3, 0xF4, 0xF5, 0xF7, 0xF8, 0xFF], np.uint8)
@@ -900,7 +912,7 @@ def test_batch_boundary_alphabet_length_4_and_5(u8):
 
 
 @pytest.mark.gpu
-def test_batch_length_mix_far_from_stationary(u8):
+def test_batch_length_mix_far_from_stationary(u8, batch_tile):
     """Length mixes where string index and byte position are far from proportional, so the
     interpolated first round of each wave's boundary search misses and the search falls
     back to 64-ary rounds; every launch shape gives the oracle's results."""
@@ -933,7 +945,7 @@ def test_batch_length_mix_far_from_stationary(u8):
 
 
 @pytest.mark.gpu
-def test_batch_paper_randomized_inputs(u8):
+def test_batch_paper_randomized_inputs(u8, batch_tile):
     """The paper's randomized inputs (section 7.3: code-point byte length uniform over {1},
     {1,2}, {1,2,3}, {1,2,3,4}) as 16 KiB strings, some with an injected error, equal the oracle."""
     for i, variant in enumerate(("unif1", "unif2", "unif3", "unif4")):
@@ -948,7 +960,7 @@ def test_batch_paper_randomized_inputs(u8):
         assert np.array_equal(flags.cpu().numpy(), f_o), variant
 
 
-def test_randomized_shapes_against_the_oracle(u8):
+def test_randomized_shapes_against_the_oracle(u8, batch_tile):
     """Seeded random single buffers (1- and 2-byte text most often, with random errors and a
     stray 3- or 4-byte character), batches (mixed per-string variants, log-normal or Pareto
     lengths, 0-50% errors, a prefix before offsets[0]) and chunked streams of 2-byte text."""

@@ -50,7 +50,7 @@ def test_noalloc_equals_the_allocating_entry_point(waves):
     small = rng.integers(0, 300, 5000).astype(np.int64)
     old = u8.get_config()
     try:
-        u8.set_config(batch_waves_per_cu=waves)
+        u8.set_config(batch_waves_per_cu=waves, batch_unroll=8 if waves == 3 else 4)  # 4 and 8 KiB tiles
         stream = torch.cuda.current_stream().cuda_stream or None
         for i, (lens, err) in enumerate(((big, 0.5), (small, 0.2))):
             data, offsets, expected = synth.batch_from_lengths(lens, "mixed", 100 + waves + i, err_frac=err, base=3)
