@@ -46,7 +46,19 @@ def check(req, exp, what):
     assert np.array_equal(f, exp[0]), what
 
 
-def test_serve_alone_equals_in_the_mix(sv):
+@pytest.mark.parametrize("tile", [4, 8])
+def test_serve_alone_equals_in_the_mix(sv, tile):
+    """Each request's results are the oracle's alone and in a mix (batch tiles of 4 and 8 KiB)."""
+    import paper_2010_03090_amd as u8
+    old = u8.get_config()
+    u8.set_config(batch_unroll=tile)
+    try:
+        _alone_and_in_the_mix(sv)
+    finally:
+        u8.set_config(**old)
+
+
+def _alone_and_in_the_mix(sv):
     sizes = [0, 1, 2, 3, 17, 100, 1000, 4096, 2500, 64, 1, 0, 333, 4000, 7, 900, 2048, 5, 3000, 12] * 2
     pool, expect = make_pool(sv, sizes, 41)
     probe = [1, 7, 13, 19]
