@@ -372,49 +372,80 @@ constexpr uint64_t kSlotMask = (1ull << kSlotShift) - 1;
 // one long string do not contend in compare-and-swap loops.  A wave contributes for at
 // most two strings (the one open at its start and the one open at its end), after its
 // last tile; the two arrivals are in flight together.  Lane 0.
+//
+// Atomics on one word are executed one after another across the device (about 11 ns
+// each), so a string across thousands of waves would hold up the end of the kernel by
+// as many.  When more than kFanIn waves lie strictly inside the string, those waves
+// (which hold no boundary, so no string starts in them and their own slots are free)
+// arrive in groups of kFanIn at the slot of their group's first wave; the last arrival
+// of a group carries the group's least detection on to the string's slot, which counts
+// the first wave, the last wave and one arrival per group.
+constexpr int kFanIn = 64;
+
 struct CrossWave {
   int64_t k, st, en, d;
-  int ws, we;
+  int ws, we;       // the string's first and last wave
+  int slot;         // the slot this wave arrives at: ws, or its group's first wave
+  int expect;       // arrivals that slot receives
+  int top_expect;   // arrivals the string's slot (ws) receives
   uint64_t mine, old;
 };
 
+// w: the arriving wave.
 __device__ __forceinline__ CrossWave cross_wave_begin(int64_t k, int64_t st, int64_t en, int64_t d, int64_t c0,
-                                                      const TileRuns& runs) {
-  CrossWave c{k, st, en, d, 0, 0, 0, 0};
+                                                      const TileRuns& runs, int w) {
+  CrossWave c{k, st, en, d, 0, 0, 0, 0, 0, 0, 0};
   if (k >= 0) {
     c.ws = runs.wave_of(st, c0);
     c.we = runs.wave_of(en, c0);
     c.mine = d == kNoneRel ? 0 : kSlotMask - (uint64_t)d;
+    const int inner = c.we - c.ws - 1;  // waves strictly inside the string
+    c.top_expect = inner > kFanIn ? 2 + (inner + kFanIn - 1) / kFanIn : c.we - c.ws + 1;
+    c.slot = c.ws;
+    c.expect = c.top_expect;
+    if (inner > kFanIn && w > c.ws && w < c.we) {
+      c.slot = c.ws + 1 + (w - c.ws - 1) / kFanIn * kFanIn;
+      c.expect = c.we - c.slot < kFanIn ? c.we - c.slot : kFanIn;
+    }
   }
   return c;
 }
 
-// The arrival: an atomic add, or (lowering the detection) a compare-and-swap loop.
-__device__ __forceinline__ void cross_wave_arrive(const DevArgs& a, CrossWave& c, bool lowering) {
-  if (c.k < 0 || (c.mine != 0) != lowering) return;
-  const gptr<unsigned long long> slot = a.slot + c.ws;
-  if (c.mine != 0) {
+// One arrival at a slot: an atomic add, or (lowering the detection) a compare-and-swap
+// loop; returns the word before it.  `mine` becomes 0 when it does not lower the slot's
+// detection (then the arrival is a plain add).
+__device__ __forceinline__ uint64_t slot_arrive(gptr<unsigned long long> slot, uint64_t& mine) {
+  if (mine != 0) {
     uint64_t old = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while ((old & kSlotMask) < c.mine) {
-      const uint64_t nw = (old & ~kSlotMask) + (1ull << kSlotShift) + c.mine;
+    while ((old & kSlotMask) < mine) {
+      const uint64_t nw = (old & ~kSlotMask) + (1ull << kSlotShift) + mine;
       unsigned long long seen = old;
       if (__hip_atomic_compare_exchange_strong(slot, &seen, (unsigned long long)nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT)) {
-        c.old = old;
-        return;
-      }
+                                               __HIP_MEMORY_SCOPE_AGENT))
+        return old;
       old = seen;
     }
-    c.mine = 0;  // does not lower it: a plain arrival
+    mine = 0;  // does not lower it: a plain arrival
   }
-  c.old = __hip_atomic_fetch_add(slot, 1ull << kSlotShift, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_fetch_add(slot, 1ull << kSlotShift, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void cross_wave_arrive(const DevArgs& a, CrossWave& c, bool lowering) {
+  if (c.k < 0 || (c.mine != 0) != lowering) return;
+  c.old = slot_arrive(a.slot + c.slot, c.mine);
 }
 
 __device__ __forceinline__ void cross_wave_end(const DevArgs& a, const CrossWave& c) {
-  if (c.k < 0 || (int)(c.old >> kSlotShift) + 1 != c.we - c.ws + 1) return;
-  const uint64_t prev = c.old & kSlotMask;
-  const uint64_t best = prev > c.mine ? prev : c.mine;
-  __hip_atomic_exchange(a.slot + c.ws, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (c.k < 0 || (int)(c.old >> kSlotShift) + 1 != c.expect) return;
+  uint64_t best = (c.old & kSlotMask) > c.mine ? (c.old & kSlotMask) : c.mine;
+  __hip_atomic_exchange(a.slot + c.slot, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (c.slot != c.ws) {  // the last of a group: the group's arrival at the string's slot
+    uint64_t m = best;
+    const uint64_t old = slot_arrive(a.slot + c.ws, m);
+    if ((int)(old >> kSlotShift) + 1 != c.top_expect) return;
+    best = (old & kSlotMask) > m ? (old & kSlotMask) : m;
+    __hip_atomic_exchange(a.slot + c.ws, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   const gptr<const uint8_t> s = a.data + c.st;
   write_result(a, c.k, [s](int64_t q) { return (uint32_t)s[q]; }, c.en - c.st,
                best == 0 ? kNoneRel : (int64_t)(kSlotMask - best));
@@ -838,8 +869,10 @@ __global__ __launch_bounds__(64) void batch_main(BatchArgs a0, int level) {
   if (lane0 && (first_k >= 0 || open_k >= 0)) {
     const int64_t tiles_u = (uniform(hi_v) + 1 - c0 + kTile - 1) / kTile;
     const TileRuns runs_u{tiles_u, (int)((tiles_u + gridDim.x - 1) / gridDim.x), kTile};
-    CrossWave c1 = cross_wave_begin(first_k, uniform(first_st_v), uniform(first_en_v), uniform(first_d_v), c0, runs_u);
-    CrossWave c2 = cross_wave_begin(open_k, uniform(open_st_v), uniform(final_en_v), open_d, c0, runs_u);
+    const int wl = (int)logical_wave(blockIdx.x, gridDim.x);
+    CrossWave c1 =
+        cross_wave_begin(first_k, uniform(first_st_v), uniform(first_en_v), uniform(first_d_v), c0, runs_u, wl);
+    CrossWave c2 = cross_wave_begin(open_k, uniform(open_st_v), uniform(final_en_v), open_d, c0, runs_u, wl);
     cross_wave_arrive(a, c1, false);
     cross_wave_arrive(a, c2, false);
     cross_wave_arrive(a, c1, true);

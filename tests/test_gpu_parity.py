@@ -423,6 +423,44 @@ def test_batch_pieces_at_tile_edges_inside_long_strings(u8, batch_tile):
         u8.set_config(**old)
 
 
+def test_batch_long_strings_across_thousands_of_waves(u8, batch_tile):
+    """Strings of 32-64 MiB spanning hundreds to thousands of waves (whose arrivals are
+    gathered in groups), valid or with one error near their start, middle or end, or cut
+    short at the end; short strings around them; several grid sizes."""
+    rng = np.random.default_rng(57)
+    lens = np.array([5, 64 << 20, 3, (32 << 20) + 17, 0, 1000, (48 << 20) + 5, 2], np.int64)
+    data, offsets, _ = synth.batch_from_lengths(lens, ["cjk", "emoji", "ascii", "latin", "ascii", "mixed", "cjk",
+                                                       "ascii"], 58)
+    f0, e0 = oracle.first_error_batch(data, offsets)
+    assert (f0 == 1).all()
+    cases = [("valid", data)]
+    for name in ("start", "middle", "end"):
+        d = data.copy()
+        for k in (1, 3, 6):
+            s0, s1 = int(offsets[k]), int(offsets[k + 1])
+            lo = {"start": 4096, "middle": (s1 - s0) // 2, "end": s1 - s0 - 64}[name]
+            synth.inject_random(d[s0:s1], int(rng.integers(0, 2**62)), lo=lo, hi=lo + 64)
+        cases.append((name, d))
+    d = data.copy()
+    d[int(offsets[2]) - 1] = 0xE4  # string 1 ends inside a character
+    cases.append(("cut", d))
+    old = u8.get_config()
+    try:
+        for name, d in cases:
+            f_o, e_o = oracle.first_error_batch(d, offsets)
+            td, to = dev(d), dev(offsets)
+            for waves in (4, 16, 64):
+                say(f"case: long strings {name}, batch_waves_per_cu {waves}")
+                u8.set_config(batch_waves_per_cu=waves)
+                flags, ferr = u8.validate_batch(td, to)
+                torch.cuda.synchronize()
+                assert np.array_equal(ferr.cpu().numpy(), e_o), (name, waves)
+                assert np.array_equal(flags.cpu().numpy(), f_o), (name, waves)
+            del td
+    finally:
+        u8.set_config(**old)
+
+
 def test_batch_graph_replays(u8, batch_tile):
     """The captured-graph entry point: every replay, with eager work between them, equals the oracle."""
     cases = []
