@@ -37,6 +37,7 @@
 // those waves to arrive (an arrival count kept in the same 64-bit word) writes its
 // result and resets the slot, so the workspace is clean again when the kernel ends.
 #include "common.hpp"
+#include "cross_wave_plan.hpp"
 #include "lookup.hpp"
 
 namespace utf8v {
@@ -372,15 +373,7 @@ constexpr uint64_t kSlotMask = (1ull << kSlotShift) - 1;
 // one long string do not contend in compare-and-swap loops.  A wave contributes for at
 // most two strings (the one open at its start and the one open at its end), after its
 // last tile; the two arrivals are in flight together.  Lane 0.
-//
-// Atomics on one word are executed one after another across the device (about 11 ns
-// each), so a string across thousands of waves would hold up the end of the kernel by
-// as many.  When more than kFanIn waves lie strictly inside the string, those waves
-// (which hold no boundary, so no string starts in them and their own slots are free)
-// arrive in groups of kFanIn at the slot of their group's first wave; the last arrival
-// of a group carries the group's least detection on to the string's slot, which counts
-// the first wave, the last wave and one arrival per group.
-constexpr int kFanIn = 64;
+// A string across more than kFanIn + 1 waves is reported in groups (cross_wave_plan.hpp).
 
 struct CrossWave {
   int64_t k, st, en, d;
@@ -399,14 +392,10 @@ __device__ __forceinline__ CrossWave cross_wave_begin(int64_t k, int64_t st, int
     c.ws = runs.wave_of(st, c0);
     c.we = runs.wave_of(en, c0);
     c.mine = d == kNoneRel ? 0 : kSlotMask - (uint64_t)d;
-    const int inner = c.we - c.ws - 1;  // waves strictly inside the string
-    c.top_expect = inner > kFanIn ? 2 + (inner + kFanIn - 1) / kFanIn : c.we - c.ws + 1;
-    c.slot = c.ws;
-    c.expect = c.top_expect;
-    if (inner > kFanIn && w > c.ws && w < c.we) {
-      c.slot = c.ws + 1 + (w - c.ws - 1) / kFanIn * kFanIn;
-      c.expect = c.we - c.slot < kFanIn ? c.we - c.slot : kFanIn;
-    }
+    const ArrivalPlan p = arrival_plan(c.ws, c.we, w);
+    c.slot = p.slot;
+    c.expect = p.expect;
+    c.top_expect = p.top_expect;
   }
   return c;
 }

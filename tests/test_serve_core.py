@@ -142,3 +142,12 @@ def test_scheduler_under_thread_sanitizer(tmp_path):
     assert r.returncode == 0, report
     assert "ThreadSanitizer" not in r.stderr, report
     assert "scheduler ok" in r.stdout, report
+
+
+def test_cross_wave_arrival_plan(tmp_path):
+    """The batch kernel's plan of where the waves of a long string report (grouped arrivals):
+    checked for every span up to 5000 waves by tests/cross_wave_check.cpp, built with g++."""
+    exe = str(tmp_path / "cross_wave_check")
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-Wall", "-o", exe, os.path.join(HERE, "cross_wave_check.cpp")])
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "arrival plan ok" in r.stdout, r.stdout + r.stderr
