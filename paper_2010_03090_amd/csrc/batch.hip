@@ -7,8 +7,9 @@
 // character relative to the string start, or -1.
 //
 // One launch does everything.  Work is split by bytes, not by strings: the
-// byte range [offsets[0], offsets[n]] is cut into 4 KiB tiles and a persistent
-// grid of one-wave workgroups gives each wave a contiguous run of tiles, so a
+// byte range [offsets[0], offsets[n]] is cut into wave tiles (4 or 8 KiB, a launch
+// setting) and a persistent grid of one-wave workgroups gives each wave a contiguous
+// run of tiles, so a
 // 64 MiB string and a million 64-byte strings load-balance alike.  A tile goes
 // from global memory straight into one of the wave's two LDS buffers (the next
 // tile's loads fill the other one while this tile is checked), preceded there by
