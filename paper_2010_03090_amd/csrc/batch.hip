@@ -9,10 +9,9 @@
 // One launch does everything.  Work is split by bytes, not by strings: the
 // byte range [offsets[0], offsets[n]] is cut into wave tiles (4 or 8 KiB, a launch
 // setting) and a persistent grid of one-wave workgroups gives each wave a contiguous
-// run of tiles, so a
-// 64 MiB string and a million 64-byte strings load-balance alike.  A tile goes
-// from global memory straight into one of the wave's two LDS buffers (the next
-// tile's loads fill the other one while this tile is checked), preceded there by
+// run of tiles, so a 64 MiB string and a million 64-byte strings load-balance alike.
+// A tile goes from global memory straight into one of the wave's two LDS buffers (the
+// next tile's loads fill the other one while this tile is checked), preceded there by
 // the 16 bytes before it.
 //
 // Per tile the wave first runs the single-buffer checks of section 6 over the tile
